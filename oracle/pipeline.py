@@ -1,0 +1,69 @@
+"""The whole stream through the oracle: windows -> pose forward -> anchoring -> focus -> maps
+(test infrastructure only).  See oracle.vit and oracle.motion for the steps."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import motion, vit
+
+
+def run_stream(frames: np.ndarray, weights: dict, heads: int, window: int, overlap: int,
+               K, n_points: int = 15, sigma: float = 1.0, sigma_min: float = 0.5,
+               sigma_max: float | None = None, anchor_mode: int = motion.ANCHOR_YAW,
+               precision: str = "fp64", windows=None, maps: bool = True, patch: int = 14):
+    """Run the oracle on one stream of frames [N,3,H,W].
+
+    windows: optionally restrict to the first `windows` windows (large configs).
+    Returns dict(schedule, pose9 [per window], T_loc [per window], T_w, track, maps, Z, argmax).
+    """
+    fx, fy, cx, cy = K
+    N, _, H, W = frames.shape
+    if sigma_max is None:
+        sigma_max = 4.0 * max(H, W)
+    sched = motion.window_schedule(N, window, overlap)
+    if windows is not None:
+        sched = sched[:windows]
+    p9s, Tls = [], []
+    for win in sched:
+        p9 = vit.forward_window(frames[win["start"]:win["start"] + win["size"]], weights, heads,
+                                patch, precision)
+        p9s.append(p9)
+        Tls.append(np.stack([vit.pose9_to_T(r) for r in p9]))
+    T_w = motion.chain_windows(sched, Tls, anchor_mode)
+    track = motion.focus_track(T_w, fx, fy, cx, cy)
+    out = dict(schedule=sched, pose9=p9s, T_loc=Tls, T_w=T_w, track=track)
+    if maps:
+        Ms, Zs, am = [], [], []
+        for t in range(T_w.shape[0]):
+            pts = motion.map_points(t, T_w, track, n_points, fx, fy, cx, cy, sigma, sigma_min,
+                                    sigma_max)
+            M, Z, a = motion.focus_map(pts, H, W)
+            Ms.append(M.astype(np.float32))
+            Zs.append(Z)
+            am.append(a)
+        out.update(maps=np.stack(Ms) if Ms else np.zeros((0, H, W), np.float32),
+                   Z=np.array(Zs), argmax=np.array(am))
+    return out
+
+
+def run_poses(T_w2c: np.ndarray, K, height: int, width: int, n_points: int = 15,
+              sigma: float = 1.0, sigma_min: float = 0.5, sigma_max: float | None = None,
+              maps: bool = True):
+    """Focus and maps for world poses given directly (the 'any pose estimator' entry)."""
+    fx, fy, cx, cy = K
+    if sigma_max is None:
+        sigma_max = 4.0 * max(height, width)
+    track = motion.focus_track(T_w2c, fx, fy, cx, cy)
+    out = dict(T_w=T_w2c, track=track)
+    if maps:
+        Ms, Zs, am = [], [], []
+        for t in range(T_w2c.shape[0]):
+            pts = motion.map_points(t, T_w2c, track, n_points, fx, fy, cx, cy, sigma, sigma_min,
+                                    sigma_max)
+            M, Z, a = motion.focus_map(pts, height, width)
+            Ms.append(M.astype(np.float32))
+            Zs.append(Z)
+            am.append(a)
+        out.update(maps=np.stack(Ms) if Ms else np.zeros((0, height, width), np.float32),
+                   Z=np.array(Zs), argmax=np.array(am))
+    return out
