@@ -1,0 +1,177 @@
+"""Benchmark: frames/s of the motion-focus path (pose + focus + map) on one MI355X.
+
+One step = one synthetic stream of the small workload (64 frames 3x280x504, windows of 16 frames
+sharing 8, 12-layer D=384 ViT in BF16) pushed from device memory: every window's forward in one
+fused batch, FP64 anchoring, focus and focus maps, all 64 results polled (maps into device
+memory).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import mf_synth  # noqa: E402
+
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+
+
+def global_attention_flops(wl) -> float:
+    """Algorithmic flops of one global-attention launch: every window of the stream, 4 T^2 D each
+    (QK^T and PV, 2 flops per multiply-add), T = frames per window x tokens per frame."""
+    from oracle import motion  # schedule only (no arithmetic of the path)
+    sched = motion.window_schedule(wl.frames, wl.window, wl.overlap)
+    n = wl.tokens_per_frame
+    return sum(4.0 * (w["size"] * n) ** 2 * wl.model.dim for w in sched)
+
+
+def path_flops(wl) -> float:
+    from oracle import motion
+    sched = motion.window_schedule(wl.frames, wl.window, wl.overlap)
+    n, D, F, L = wl.tokens_per_frame, wl.model.dim, wl.model.mlp, wl.model.depth
+    tot = 0.0
+    for w in sched:
+        T = w["size"] * n
+        gemm = 2.0 * T * D * (3 * D + D + 2 * F)
+        tot += L * gemm + (L // 2) * 4.0 * T * T * D + (L - L // 2) * 4.0 * T * n * D
+        tot += 2.0 * w["size"] * (wl.height // 14) * (wl.width // 14) * 588 * D
+    return tot
+
+
+def run_gpu(wl, precision: str, steps: int, warmup: int, sigma: float):
+    import torch
+    import paper_2601_07154_amd as mfp
+    blob = mf_synth.make_weights(wl.model, wl.seed_weights)
+    frames = torch.from_numpy(mf_synth.workload_frames(wl)).cuda()
+    rows = mfp.rows_per_frame(wl.height, wl.width)
+    sched_frames = sum(w["size"] for w in __import__("oracle").motion.window_schedule(wl.frames, wl.window,
+                                                                                        wl.overlap))
+    eng = mfp.Engine.from_model(wl.model, blob, precision=precision, max_tokens=sched_frames * rows + 64)
+    K = (wl.fx, wl.fy, wl.cx, wl.cy)
+    maps = torch.empty((wl.frames, wl.height, wl.width), device="cuda", dtype=torch.float32)
+    sids = [eng.open_stream(wl.height, wl.width, wl.window, wl.overlap, K, sigma=sigma, ring_frames=wl.frames,
+                            result_frames=wl.frames) for _ in range(steps + warmup)]
+    recs_all = []
+
+    def step(sid):
+        eng.push_frames(sid, frames, eos=True)
+        eng.sync()
+        got = 0
+        while got < wl.frames:
+            r, st = eng.poll(sid, wl.frames - got, maps[got:])
+            got += len(r)
+            recs_all.append(r)
+            if st != 0 and got < wl.frames:
+                raise RuntimeError("stream ended early")
+        return got
+
+    for i in range(warmup):
+        step(sids[i])
+    recs_all.clear()
+    eng.profile(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    for i in range(steps):
+        n += step(sids[warmup + i])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = eng.profile(0)
+    stats = eng.stats()
+    recs = np.concatenate(recs_all)
+    lat = (recs["t_ready"] - recs["t_push"]) * 1e3
+    for sid in sids:   # drain: releases the streams
+        eng.poll(sid, 1)
+    first = recs[:wl.frames]
+    eng.close()
+    return dict(frames=n, seconds=dt, prof=prof, stats=stats, lat=lat, first=first)
+
+
+def cpu_baseline(wl, sigma: float):
+    """The FP64 oracle on a bounded sample: window 0 (16 frames, all layers) plus chaining, focus
+    and maps of its frames; frames/s extrapolated to the whole stream (7 windows per 64 frames)."""
+    from oracle import motion, pipeline, vit
+    blob = mf_synth.make_weights(wl.model, wl.seed_weights)
+    w = vit.unpack_weights(blob, wl.model.depth, wl.model.dim, wl.model.mlp)
+    frames = mf_synth.workload_frames(wl, wl.window)
+    t0 = time.perf_counter()
+    out = pipeline.run_stream(frames, w, wl.model.heads, wl.window, wl.overlap, (wl.fx, wl.fy, wl.cx, wl.cy),
+                              sigma=sigma)
+    dt = time.perf_counter() - t0
+    nwin = len(motion.window_schedule(wl.frames, wl.window, wl.overlap))
+    fps = wl.frames / (nwin * dt)
+    return fps, dt, out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--sigma", type=float, default=1000.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        sys.exit(2)
+    wl = mf_synth.SMALL
+    r = run_gpu(wl, args.precision, args.steps, args.warmup, args.sigma)
+    fps = r["frames"] / r["seconds"]
+    ms_step = r["seconds"] * 1e3 / args.steps
+    res = {
+        "metric": "frames/sec pose+focus (BF16/FP8 vs FP32 at stated pose error); p50/p99 latency",
+        "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic (seeded uniform pixels, seeded N(0,0.02) random-init weights)",
+        "config": {"workload": wl.name, "frames": wl.frames, "height": wl.height, "width": wl.width,
+                   "window": wl.window, "overlap": wl.overlap, "layers": wl.model.depth, "dim": wl.model.dim,
+                   "heads": wl.model.heads, "mlp": wl.model.mlp, "windows_per_step": 7,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": float(np.percentile(r["lat"], 50)), "p99": float(np.percentile(r["lat"], 99))},
+        "path_tflops": path_flops(wl) * args.steps / r["seconds"] / 1e12,
+    }
+    prof = r["prof"]
+    calls = max(1, prof["attn_global_calls"])
+    avg_ms = prof["attn_global_ms"] / calls
+    flops = global_attention_flops(wl)
+    ach = flops / (avg_ms * 1e-3) / 1e12
+    res["roofline"] = {"kernel": "global flash attention (attn_kernel<bf16,64>)", "bound": "mfma",
+                       "achieved": ach, "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
+                       "frac": ach / PEAK_TFLOPS[args.precision], "traffic": None,
+                       "avg_launch_ms": avg_ms, "launches": prof["attn_global_calls"],
+                       "flops_per_launch": flops}
+    res["stage_ms_per_step"] = {"attn_global": prof["attn_global_ms"] / args.steps,
+                                "attn_frame": prof["attn_frame_ms"] / args.steps,
+                                "gemm": prof["gemm_ms"] / args.steps}
+    if not args.no_fp32 and args.precision != "fp32":
+        f = run_gpu(wl, "fp32", 2, 1, args.sigma)
+        res["fp32_value"] = f["frames"] / f["seconds"]
+        res["speedup_vs_fp32"] = fps / res["fp32_value"]
+    if not args.no_cpu_baseline:
+        cfps, cdt, out = cpu_baseline(wl, args.sigma)
+        res["cpu_baseline"] = {"value": cfps, "unit": "frames/s", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                               "kind": "oracle",
+                               "sample": f"window 0 of the workload (16 frames, all 12 layers, FP64) + anchoring/focus/maps: "
+                                         f"{cdt:.1f} s, scaled to 7 windows per 64 frames"}
+        # pose error of the timed GPU run against the FP64 oracle on window 0
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from gpu_util import dir_err_deg, rot_err_deg
+        Tg = r["first"]["T_w2c"].reshape(-1, 4, 4)[:wl.window]
+        Tr = out["T_w"][:wl.window]
+        res["pose_error_window0"] = {"rot_deg_max": float(rot_err_deg(Tg[:, :3, :3], Tr[:, :3, :3]).max()),
+                                     "tdir_deg_max": float(dir_err_deg(Tg[:, :3, 3], Tr[:, :3, 3]).max())}
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/* mf.h -- C ABI of the MI355X motion-focus library (libmfocus.so).
+ *
+ * The library turns video streams into per-frame camera poses and motion-focus points and
+ * maps, following "Motion Focus Recognition in Fast-Moving Egocentric Video":
+ *   - sliding-window ("sliding batch") inference of a multi-view ViT pose regressor over
+ *     windows of L frames sharing O frames with their predecessor (Sec. 2.2);
+ *   - incremental anchoring of each window's local poses to the previous trajectory at a
+ *     shared frame, propagating only yaw and translation, in FP64; only frames not emitted
+ *     before are emitted (Sec. 2.2);
+ *   - the focus point: camera centre (Eq. 1), second difference (Eq. 2-3), rotation into
+ *     the current camera (Eq. 4), pinhole projection with intrinsics K (Eq. 5-6);
+ *   - the focus map: a normalised sum of Gaussians at the last N motion points (Eq. 7).
+ *
+ * Conventions
+ *   - Poses are world-to-camera 4x4 row-major doubles, OpenCV axes (x right, y down,
+ *     z forward).  The world frame is the first window's frame; gravity is its y axis.
+ *   - Frames are fp32 RGB in [0,1), planar [n][3][H][W], H and W multiples of 14.
+ *   - Intrinsics are in model-input pixels.
+ *   - Every call returns an mf_status; 0 is success, negatives are errors.  No C++
+ *     exception or abort crosses the ABI; mf_last_error() gives a thread-local message.
+ *   - All calls on one engine are thread-safe.
+ */
+#ifndef MF_H
+#define MF_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mf_status;
+#define MF_OK 0
+#define MF_EINVAL -1    /* bad argument, shape or call order */
+#define MF_ENOMEM -2    /* does not fit the HBM budget, now or ever */
+#define MF_EAGAIN -3    /* not now: nothing ready, ring full, or budget in use by other streams */
+#define MF_ECLOSED -4   /* stream closed (end of stream reached) */
+#define MF_EDEVICE -5   /* HIP error; see mf_last_error() */
+#define MF_ENOTFOUND -6 /* unknown stream id */
+
+/* precisions of the ViT forward (the chaining and focus stages are always FP64) */
+#define MF_FP32 0       /* fp32 operands on fp32 MFMA */
+#define MF_BF16 1       /* bf16 GEMM/attention operands, fp32 accumulation/softmax/LayerNorm */
+
+/* anchoring modes */
+#define MF_ANCHOR_YAW 0 /* lock pitch and roll, propagate yaw and translation (the paper) */
+#define MF_ANCHOR_SE3 1 /* full rigid alignment (no lock) */
+
+/* push flags */
+#define MF_EOS 1          /* these are the stream's last frames */
+#define MF_DEVICE_PTR 2   /* the pointer is device memory (HIP) */
+#define MF_POSES_LOCAL 4  /* mf_push_poses: poses of one window in its own local frame */
+
+typedef struct mf_engine mf_engine;
+
+typedef struct mf_model_cfg {
+  int32_t depth;      /* transformer blocks, alternating frame-wise (even) / global (odd) */
+  int32_t dim;        /* width D: 128, 256, 384, 512, 768 or 1024 */
+  int32_t heads;      /* D / heads must be 32 or 64 */
+  int32_t mlp;        /* MLP hidden width (multiple of 128) */
+  int32_t patch;      /* must be 14 */
+  int32_t precision;  /* MF_FP32 or MF_BF16 */
+} mf_model_cfg;
+
+typedef struct mf_runtime_cfg {
+  int32_t device;               /* HIP device ordinal */
+  int32_t threaded;             /* 1: an internal scheduler thread runs batches as windows become
+                                   ready; 0: batches run inside mf_engine_step / mf_engine_sync */
+  int64_t max_tokens_per_batch; /* token rows of one fused batch (0: 262144) */
+  uint64_t hbm_budget_bytes;    /* device memory the engine may use (0: 80% of free memory) */
+  void* stream;                 /* hipStream_t to run on, or NULL for an engine-owned stream */
+} mf_runtime_cfg;
+
+typedef struct mf_stream_cfg {
+  int32_t height, width;        /* model-input frame size, multiples of 14 */
+  int32_t window, overlap;      /* L and O, 1 <= O < L: consecutive windows share O frames */
+  double fx, fy, cx, cy;        /* pinhole intrinsics (Eq. 5) */
+  int32_t n_points;             /* N of Eq. 7, 1..32 */
+  int32_t anchor_mode;          /* MF_ANCHOR_YAW or MF_ANCHOR_SE3 */
+  double sigma;                 /* Eq. 7 scale: spread = clip(sigma * |a_w,i|, sigma_min, sigma_max) px */
+  double sigma_min, sigma_max;  /* 0 => 0.5 and 4 * max(H, W) */
+  int32_t emit_maps;            /* 1: render the focus map of every emitted frame */
+  int32_t ring_frames;          /* device frame ring capacity (0: 2L + 8) */
+  int32_t result_frames;        /* results (and maps) held until polled (0: 4L) */
+  int32_t reserved;
+} mf_stream_cfg;
+
+/* One emitted frame.  valid bit 0: focus point defined (t >= 2, |a_w| > 0, a_z not ~0);
+   bit 1: the map is non-zero. */
+typedef struct mf_focus {
+  int64_t frame;            /* frame index within the stream */
+  int32_t window;           /* window that emitted it */
+  int32_t valid;
+  double T_w2c[16];         /* chained world-to-camera pose */
+  float pose9[9];           /* raw head output (t3, quaternion xyzw, fov2); zeros for pushed poses */
+  int32_t peak_x, peak_y;   /* argmax of the map (ties: smallest y*W + x) */
+  float reserved;
+  double a_world[3];        /* Eq. 3 */
+  double a_cam[3];          /* Eq. 4 */
+  double u, v;              /* Eq. 6 */
+  double s;                 /* |a_world|, the motion magnitude of Eq. 7 */
+  double t_push, t_ready;   /* seconds since engine creation: frame pushed / result complete */
+} mf_focus;
+
+typedef struct mf_stats {
+  int64_t frames_pushed, frames_emitted, windows_run, batches_run;
+  int64_t tokens_run;
+  int32_t streams_open, streams_pending;
+  uint64_t hbm_used_bytes, hbm_budget_bytes;
+  double gpu_ms;            /* device time of all batches (HIP events) */
+} mf_stats;
+
+/* Create an engine: copies the fp32 weight blob (caller keeps ownership) to the device,
+ * allocates the per-batch workspace, creates the stream and (threaded) the scheduler.
+ * Blob order: W_p[588,D] b_p c_ref c_other, per layer {ln1.g ln1.b W_qkv[D,3D] b_qkv W_o b_o
+ * ln2.g ln2.b W_1[D,F] b_1 W_2[F,D] b_2}, lnf.g lnf.b H_1[D,D] h_1 H_2[D,9] h_2;
+ * linear layers stored [in, out].  n_floats must match exactly (MF_EINVAL otherwise). */
+mf_status mf_engine_create(const mf_model_cfg* model, const float* weights, size_t n_floats,
+                           const mf_runtime_cfg* rt, mf_engine** out);
+/* Stop the scheduler, free every device allocation.  Safe on NULL. */
+void mf_engine_destroy(mf_engine* e);
+
+/* Admit a stream.  MF_EAGAIN: the HBM budget is held by other streams now;
+ * MF_ENOMEM: it can never fit; MF_EINVAL: bad sizes. */
+mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream_id);
+
+/* Append n frames [n][3][H][W] (host or, with MF_DEVICE_PTR, device memory).  The frames
+ * are copied before return.  MF_EAGAIN: the frame ring is full (poll, then retry);
+ * MF_ECLOSED after end of stream. */
+mf_status mf_push_frames(mf_engine* e, int32_t stream_id, const float* rgb, int32_t n, int32_t flags);
+
+/* The "any pose estimator" entry (Sec. 1, Sec. 2.3): push poses instead of frames.
+ * Without MF_POSES_LOCAL: n world poses of frames first_frame .. first_frame+n-1, which must
+ * continue the stream.  With MF_POSES_LOCAL: the n local poses of one window starting at
+ * frame first_frame; the engine anchors them to the previous window at the last frame it
+ * emitted (which the window must contain) and emits the frames not emitted before.
+ * A stream takes either frames or poses, not both. */
+mf_status mf_push_poses(mf_engine* e, int32_t stream_id, const double* T_w2c, int32_t n,
+                        int64_t first_frame, int32_t flags);
+
+/* Copy up to cap completed frames, in frame order, each exactly once.  maps (nullable):
+ * [cap][H][W] fp32 host memory, or device memory with MF_DEVICE_PTR in maps_flags.
+ * MF_EAGAIN: nothing ready now; MF_ECLOSED: closed and fully drained (the id is released). */
+mf_status mf_poll_focus(mf_engine* e, int32_t stream_id, mf_focus* out, int32_t cap,
+                        int32_t* n_out, float* maps, int32_t maps_flags);
+
+/* End of stream: no more pushes; the tail window is scheduled; results stay pollable. */
+mf_status mf_close_stream(mf_engine* e, int32_t stream_id);
+
+/* Non-threaded engines: run one batch of ready windows (n_windows may be NULL).
+ * Threaded engines: MF_EINVAL. */
+mf_status mf_engine_step(mf_engine* e, int32_t* n_windows);
+/* Block until every ready window has been run and its results are pollable. */
+mf_status mf_engine_sync(mf_engine* e);
+mf_status mf_engine_stats(mf_engine* e, mf_stats* out);
+
+const char* mf_status_str(mf_status s);
+const char* mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

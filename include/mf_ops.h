@@ -1,0 +1,67 @@
+/* mf_ops.h -- op-level entry points of libmfocus.so: single stages of the path, exposed so that
+ * each can be checked and timed on its own.  Same status and error conventions as mf.h.
+ *
+ * Device layouts used below (T = float for MF_FP32, bfloat16 for MF_BF16):
+ *   token rows  : a window of S frames occupies S * npad rows, frame f at rows f*npad ..;
+ *                 row 0 of a frame is its camera token, rows 1..P its patches (grid row-major),
+ *                 rows P+1 .. npad-1 padding; npad = P + 1 rounded up to a multiple of 8.
+ *   Q, K        : head-major [heads][mpad][hd]
+ *   Vt          : transposed [heads][hd][mpad]
+ *   O           : [rows][dim], head h in columns h*hd .. h*hd+hd-1
+ * mpad must exceed every row a segment can touch by 256 (rows beyond the data must hold
+ * finite values: they are read and masked).
+ */
+#ifndef MF_OPS_H
+#define MF_OPS_H
+#include "mf.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Rows per frame in the token layout (npad above) for an H x W frame. */
+int32_t mf_rows_per_frame(int32_t height, int32_t width);
+
+/* The ViT forward of one window (Sec. 2.2's per-window pose inference) on S frames already in
+ * device memory ([S][3][H][W] fp32).  max_layers < 0 runs the whole network and writes
+ * pose9 [S][9] (fp32) and T [S][16] (world(window)-to-camera, fp64); otherwise only the
+ * patch embedding and the first max_layers blocks run.  tokens (nullable, host):
+ * the residual stream [S * npad][dim] fp32 after the last block run.  Host outputs are
+ * nullable.  MF_EAGAIN while the engine is running a batch. */
+mf_status mf_forward_window(mf_engine* e, const float* frames_dev, int32_t S, int32_t height,
+                            int32_t width, int32_t max_layers, float* pose9, double* T, float* tokens);
+
+/* Diagnostics: copy the first `bytes` of an internal buffer, as left by the last batch or
+ * mf_forward_window, to host memory.  which: 0 residual X (fp32 [rows][dim]), 1 LayerNorm output
+ * ([rows][dim]), 2 Q, 3 K, 4 Vt (layouts above; mpad is max_tokens_per_batch rounded up to 8,
+ * plus 256), 5 attention output O
+ * ([rows][dim]), 6 MLP hidden / patch matrix ([rows][max(mlp, 640)]); element type T of the
+ * engine's precision except X.  MF_EINVAL beyond the buffer. */
+mf_status mf_debug_copy(mf_engine* e, int32_t which, void* host, size_t bytes);
+
+/* Per-kernel timing (HIP events on the engine's stream, summed over batches since the last
+ * reset).  enable: 1 start and reset, 0 stop and reset, -1 just read. */
+mf_status mf_profile(mf_engine* e, int32_t enable, double* attn_global_ms, int64_t* attn_global_calls,
+                     double* attn_frame_ms, double* gemm_ms);
+
+/* Attention softmax(Q K^T / sqrt(hd)) V per head within segments.  segs (host): nseg rows of
+ * {base, nf, n, npad}: tokens base .. base + nf*npad - 1, frames of n valid tokens every npad
+ * rows (keys in padding rows are masked).  Q, K, Vt, O: device, layouts above.
+ * Frame-wise layers use nf = 1 per frame; global layers one segment per window. */
+mf_status mf_op_attention(int32_t precision, int32_t head_dim, int32_t heads, int32_t dim,
+                          const void* q, const void* k, const void* vt, void* o, int64_t mpad,
+                          const int32_t* segs, int32_t nseg, void* stream);
+
+/* C[M][N] = A[M][K] Bt[N][K]^T + bias (fp32 out; bias nullable).  A, Bt in the precision's
+ * type, device memory; N a multiple of 128; K a multiple of 64 (bf16) / 32 (fp32). */
+mf_status mf_op_gemm(int32_t precision, const void* A, const void* Bt, const float* bias, float* C,
+                     int32_t M, int32_t N, int32_t K, void* stream);
+
+/* y = LayerNorm(x) * g + b over rows of dim (eps 1e-6), x fp32, y in the precision's type. */
+mf_status mf_op_layernorm(int32_t precision, const float* x, void* y, const float* g, const float* b,
+                          int64_t rows, int32_t dim, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_OPS_H */

@@ -1,0 +1,267 @@
+// Fused flash attention for gfx950 over token segments (frame-wise and global layers).
+//
+// A segment is nf frames of n valid tokens stored every npad rows (npad = n rounded up to 8,
+// so every frame starts 16-byte aligned in the transposed V layout).  Frame-wise layers use
+// one segment per frame, global layers one segment per window; keys in the padding rows
+// between frames are masked.  softmax(Q K^T / sqrt(hd)) V is computed per head with the
+// running-max rescaling of flash attention: scores never leave registers.
+//
+// Each workgroup (4 waves) takes 128 queries of one segment and one head; each wave owns
+// 32 queries.  Scores are computed transposed, S^T = K Q^T, so that each lane holds one query
+// column: the row max is a reduction over the lane's 16 values plus one exchange between
+// the two lane halves.  The probabilities feed O^T = V^T P^T directly from registers as the
+// B operand (their k order, {4g..4g+3, 8+4g..8+4g+3}, is matched by the V^T fragments read
+// from LDS).  K tiles [64 keys][hd] and V^T tiles [hd][64 keys] are staged in LDS with
+// XOR-swizzled 16-byte chunks, double-buffered.
+#include "device.h"
+#include "kernels.h"
+
+namespace mf {
+
+template <typename T, int HD>
+struct AttnCfg {
+  static constexpr int BK = 64;                          // keys per tile
+  static constexpr int KCPR = HD * (int)sizeof(T) / 16;  // 16-byte chunks per K row
+  static constexpr int VCPR = BK * (int)sizeof(T) / 16;  // 16-byte chunks per V^T row
+  static constexpr int KCH = BK * KCPR;                  // chunks per K tile
+  static constexpr int VCH = HD * VCPR;                  // chunks per V^T tile
+  static constexpr int QF = HD * (int)sizeof(T) / 32;    // 16-byte Q fragments per lane
+  static constexpr int DT = HD / 32;                     // 32-row tiles of O^T
+};
+
+// S^T (32 keys x 32 queries) += K_frag x Q^T_frag over the head dimension.
+template <typename T, int HD>
+MF_DEV void qk_tile(const uint4* sK, int key_row, const uint4* qf, int g, f32x16& s) {
+  using C = AttnCfg<T, HD>;
+#pragma unroll
+  for (int f = 0; f < C::QF; ++f) {
+    const int ch = 2 * f + g;
+    const uint4 kf = sK[key_row * C::KCPR + (ch ^ (key_row % C::KCPR))];
+    if constexpr (sizeof(T) == 2) {
+      s = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf, *(const bf16x8*)&qf[f], s, 0, 0, 0);
+    } else {
+      s = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(kf.x), __uint_as_float(qf[f].x), s, 0, 0, 0);
+      s = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(kf.y), __uint_as_float(qf[f].y), s, 0, 0, 0);
+      s = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(kf.z), __uint_as_float(qf[f].z), s, 0, 0, 0);
+      s = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(kf.w), __uint_as_float(qf[f].w), s, 0, 0, 0);
+    }
+  }
+}
+
+// O^T (32 d x 32 queries) += V^T (rows d, keys of sub-tile kb) x P^T (from the score registers).
+template <typename T, int HD>
+MF_DEV void pv_tile(const uint4* sV, int d_row, int kb, int g, const f32x16& p, f32x16& o) {
+  using C = AttnCfg<T, HD>;
+  const int sw = d_row % C::VCPR;
+  if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int j2 = 0; j2 < 2; ++j2) {
+      // keys kb*32 + 16*j2 + {4g..4g+3} (chunk c0, half g) and + 8 (chunk c0+1, half g)
+      const int c0 = 4 * kb + 2 * j2;
+      const uint2* row = (const uint2*)(sV + d_row * C::VCPR);
+      const uint2 lo = row[2 * (c0 ^ sw) + g];
+      const uint2 hi = row[2 * ((c0 + 1) ^ sw) + g];
+      uint4 vf = {lo.x, lo.y, hi.x, hi.y};
+      bf16x8 pf;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) pf[r] = (bf16)p[8 * j2 + r];
+      o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&vf, pf, o, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      // keys kb*32 + 8*jj + 4g + {0..3}: chunk 8kb + 2jj + g
+      const uint4 vf = sV[d_row * C::VCPR + ((8 * kb + 2 * jj + g) ^ sw)];
+      o = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(vf.x), p[4 * jj + 0], o, 0, 0, 0);
+      o = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(vf.y), p[4 * jj + 1], o, 0, 0, 0);
+      o = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(vf.z), p[4 * jj + 2], o, 0, 0, 0);
+      o = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(vf.w), p[4 * jj + 3], o, 0, 0, 0);
+    }
+  }
+}
+
+template <typename T, int HD>
+__global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, const T* __restrict__ K,
+                                                   const T* __restrict__ Vt, T* __restrict__ O,
+                                                   int64_t mpad, int heads, int dim,
+                                                   const AttnSeg* __restrict__ segs,
+                                                   const AttnWork* __restrict__ work, int nwork,
+                                                   float scale_log2) {
+  using C = AttnCfg<T, HD>;
+  constexpr int BK = C::BK;
+  __shared__ uint4 sK[2][C::KCH];
+  __shared__ uint4 sV[2][C::VCH];
+
+  const int nb = nwork * heads;
+  const int bid = xcd_remap(blockIdx.x, nb);
+  const int h = bid % heads, wi = bid / heads;
+  const AttnWork wk = work[wi];
+  const AttnSeg sg = segs[wk.seg];
+  const int seg_len = sg.nf * sg.npad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 5, l32 = lane & 31;
+  const int qrow = wk.q0 + wave * 32 + l32;   // this lane's query (segment-relative)
+
+  const T* Qh = Q + ((int64_t)h * mpad + sg.base) * HD;
+  const T* Kh = K + ((int64_t)h * mpad + sg.base) * HD;
+  const T* Vh = Vt + (int64_t)h * HD * mpad + sg.base;
+
+  // Q^T fragments (B operand): lane (query l32, group g) holds chunks 2f+g of its query row.
+  uint4 qf[C::QF];
+  {
+    const uint4* qr = (const uint4*)(Qh + (int64_t)qrow * HD);
+#pragma unroll
+    for (int f = 0; f < C::QF; ++f) qf[f] = qr[2 * f + g];
+  }
+
+  // Tile loaders: chunk c of the K tile is (row c / KCPR, col c % KCPR); of the V^T tile
+  // (d row c / VCPR, key chunk c % VCPR).
+  constexpr int KPT = C::KCH / 256, VPT = C::VCH / 256;
+  uint4 rk[KPT], rv[VPT];
+  auto load_tile = [&](int kt) {
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const int c = tid + i * 256, row = c / C::KCPR, col = c % C::KCPR;
+      rk[i] = *(const uint4*)(Kh + (int64_t)(kt + row) * HD + col * (16 / sizeof(T)));
+    }
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int c = tid + i * 256, row = c / C::VCPR, col = c % C::VCPR;
+      rv[i] = *(const uint4*)(Vh + (int64_t)row * mpad + kt + col * (16 / sizeof(T)));
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const int c = tid + i * 256, row = c / C::KCPR, col = c % C::KCPR;
+      sK[buf][row * C::KCPR + (col ^ (row % C::KCPR))] = rk[i];
+    }
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int c = tid + i * 256, row = c / C::VCPR, col = c % C::VCPR;
+      sV[buf][row * C::VCPR + (col ^ (row % C::VCPR))] = rv[i];
+    }
+  };
+
+  f32x16 o[C::DT];
+#pragma unroll
+  for (int t = 0; t < C::DT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) o[t][r] = 0.0f;
+  float m_run = -INFINITY, l_run = 0.0f;
+
+  const int key_end = sg.nf == 1 ? sg.n : seg_len;
+  const int ntiles = (key_end + BK - 1) / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+
+  for (int it = 0; it < ntiles; ++it) {
+    const int cur = it & 1, kt = it * BK;
+    if (it + 1 < ntiles) load_tile(kt + BK);
+
+    f32x16 s[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[kb][r] = 0.0f;
+      qk_tile<T, HD>(sK[cur], kb * 32 + l32, qf, g, s[kb]);
+    }
+    // mask keys outside the segment or in the padding rows between frames
+    const int f0 = kt / sg.npad;
+    const bool full = kt + BK <= (f0 * sg.npad + sg.n) && kt + BK <= key_end;
+    if (!full) {
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int key = kt + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+          const bool ok = key < key_end && (key % sg.npad) < sg.n;
+          if (!ok) s[kb][r] = -INFINITY;
+        }
+    }
+    float mx = -INFINITY;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[kb][r]);
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    const float m_new = fmaxf(m_run, mx * scale_log2);
+    const float alpha = exp2f(m_run - m_new);
+    m_run = m_new;
+    float ls = 0.0f;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float p = exp2f(fmaf(s[kb][r], scale_log2, -m_new));
+        s[kb][r] = p;
+        ls += p;
+      }
+    l_run = l_run * alpha + ls;
+#pragma unroll
+    for (int t = 0; t < C::DT; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[t][r] *= alpha;
+#pragma unroll
+    for (int t = 0; t < C::DT; ++t)
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) pv_tile<T, HD>(sV[cur], t * 32 + l32, kb, g, s[kb], o[t]);
+
+    if (it + 1 < ntiles) {
+      __syncthreads();
+      store_tile(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+  const float l_tot = l_run + __shfl_xor(l_run, 32, 64);
+  const float inv = 1.0f / l_tot;
+  if (qrow < seg_len) {
+    T* orow = O + (int64_t)(sg.base + qrow) * dim + h * HD;
+#pragma unroll
+    for (int t = 0; t < C::DT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int d = t * 32 + 8 * j + 4 * g;
+        if constexpr (sizeof(T) == 2) {
+          bf16x4 v;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = (bf16)(o[t][4 * j + i] * inv);
+          *(bf16x4*)(orow + d) = v;
+        } else {
+          f32x4 v;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = o[t][4 * j + i] * inv;
+          *(f32x4*)(orow + d) = v;
+        }
+      }
+  }
+}
+
+template <typename T, int HD>
+static hipError_t launch(const void* q, const void* k, const void* vt, void* o, int64_t mpad,
+                         int heads, int dim, const AttnSeg* segs, const AttnWork* work, int nwork,
+                         hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  const float scale_log2 = (float)(1.4426950408889634 / sqrt((double)HD));
+  hipLaunchKernelGGL((attn_kernel<T, HD>), dim3(nwork * heads), dim3(256), 0, s, (const T*)q,
+                     (const T*)k, (const T*)vt, (T*)o, mpad, heads, dim, segs, work, nwork,
+                     scale_log2);
+  return hipGetLastError();
+}
+
+hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void* vt, void* o,
+                     int64_t mpad, int heads, int dim, const AttnSeg* segs, const AttnWork* work,
+                     int nwork, hipStream_t s) {
+  if (dt == DT_BF16) {
+    if (hd == 64) return launch<bf16, 64>(q, k, vt, o, mpad, heads, dim, segs, work, nwork, s);
+    if (hd == 32) return launch<bf16, 32>(q, k, vt, o, mpad, heads, dim, segs, work, nwork, s);
+  } else {
+    if (hd == 64) return launch<float, 64>(q, k, vt, o, mpad, heads, dim, segs, work, nwork, s);
+    if (hd == 32) return launch<float, 32>(q, k, vt, o, mpad, heads, dim, segs, work, nwork, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mf

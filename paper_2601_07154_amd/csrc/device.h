@@ -1,0 +1,43 @@
+// Device-side helpers shared by the gfx950 kernels of the motion-focus library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#define MF_DEV __device__ __forceinline__
+
+// Map a linear workgroup id so that the ids handled by one XCD are contiguous: the
+// hardware deals workgroups round-robin over the 8 XCDs, each with its own L2.
+MF_DEV int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  const int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  return base + (b >> 3);
+}
+
+MF_DEV float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+MF_DEV float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+MF_DEV double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T> MF_DEV T from_f32(float x);
+template <> MF_DEV float from_f32<float>(float x) { return x; }
+template <> MF_DEV bf16 from_f32<bf16>(float x) { return (bf16)x; }
+template <typename T> MF_DEV float to_f32(T x) { return (float)x; }
+
+MF_DEV float gelu_erf(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }

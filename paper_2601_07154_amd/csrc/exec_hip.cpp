@@ -1,0 +1,637 @@
+// HIP executor: device weights and workspace, the per-batch launch sequence of the ViT
+// forward (patch embedding, alternating frame-wise / global blocks, pose head), then FP64
+// anchoring + focus and the focus maps.  Every arithmetic step runs in the kernels of this
+// library; the host only builds the batch tables.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "kernels.h"
+
+namespace mf {
+
+#define HIPCHECK(x)                                                              \
+  do {                                                                           \
+    hipError_t e_ = (x);                                                         \
+    if (e_ != hipSuccess) {                                                      \
+      err = std::string(#x) + " failed: " + hipGetErrorString(e_);               \
+      return MF_EDEVICE;                                                         \
+    }                                                                            \
+  } while (0)
+
+static constexpr int KP = 640;     // patch length 3*14*14 = 588 padded to the GEMM k-tile
+static constexpr int QT = 128;     // queries per attention workgroup
+
+static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+struct LayerW {
+  const float *ln1_g, *ln1_b, *b_qkv, *b_o, *ln2_g, *ln2_b, *b_1, *b_2;
+  void *Wqkv, *Wo, *W1, *W2;       // transposed [out][in], dtype
+};
+
+struct Plan {                      // host-side tables of one batch
+  std::vector<FrameDesc> frames;
+  std::vector<AttnSeg> fsegs, gsegs;
+  std::vector<AttnWork> fwork, gwork;
+  std::vector<int32_t> cam_rows;
+  int64_t mtot = 0;
+  int max_npad = 0;
+};
+
+class HipExecutor : public Executor {
+ public:
+  ~HipExecutor() override { release(); }
+
+  mf_status init(const mf_model_cfg& m, const float* w, size_t n, const mf_runtime_cfg& rt,
+                 std::string& err) override {
+    m_ = m;
+    if (m.patch != 14) { err = "patch must be 14"; return MF_EINVAL; }
+    if (m.precision != MF_FP32 && m.precision != MF_BF16) { err = "precision must be MF_FP32 or MF_BF16"; return MF_EINVAL; }
+    if (m.depth < 1 || m.heads < 1 || m.dim % m.heads) { err = "bad depth/heads/dim"; return MF_EINVAL; }
+    D_ = m.dim; H_ = m.heads; hd_ = D_ / H_; F_ = m.mlp; depth_ = m.depth;
+    if (!(D_ == 128 || D_ == 256 || D_ == 384 || D_ == 512 || D_ == 768 || D_ == 1024)) { err = "dim must be one of 128, 256, 384, 512, 768, 1024"; return MF_EINVAL; }
+    if (hd_ != 32 && hd_ != 64) { err = "head dim must be 32 or 64"; return MF_EINVAL; }
+    if (F_ <= 0 || F_ % 128) { err = "mlp must be a positive multiple of 128"; return MF_EINVAL; }
+    dt_ = m.precision == MF_BF16 ? DT_BF16 : DT_F32;
+    es_ = dt_ == DT_BF16 ? 2 : 4;
+    const size_t want = expected_floats();
+    if (n != want) { err = "weight blob has " + std::to_string(n) + " floats, the model needs " + std::to_string(want); return MF_EINVAL; }
+    HIPCHECK(hipSetDevice(rt.device));
+    device_ = rt.device;
+    if (rt.stream) { st_ = (hipStream_t)rt.stream; own_stream_ = false; }
+    else { HIPCHECK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking)); own_stream_ = true; }
+    HIPCHECK(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
+    size_t free_b = 0, total_b = 0;
+    HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+    budget_ = rt.hbm_budget_bytes ? rt.hbm_budget_bytes : (uint64_t)(free_b * 0.8);
+    mcap_ = rt.max_tokens_per_batch > 0 ? rt.max_tokens_per_batch : 262144;
+    mcap_ = align_up(mcap_, 8);
+    mpad_ = mcap_ + 256;
+    fcap_ = mcap_ / 8 + 64;
+    if (workspace_bytes() + weight_bytes() > budget_) {
+      err = "weights + workspace (" + std::to_string(workspace_bytes() + weight_bytes()) + " bytes) exceed the HBM budget";
+      return MF_ENOMEM;
+    }
+    mf_status rc = load_weights(w, n, err);
+    if (rc != MF_OK) return rc;
+    rc = alloc_workspace(err);
+    if (rc != MF_OK) return rc;
+    HIPCHECK(hipEventCreate(&ev0_));
+    HIPCHECK(hipEventCreate(&ev1_));
+    return MF_OK;
+  }
+
+  uint64_t fixed_bytes() const override { return weight_bytes() + workspace_bytes(); }
+  uint64_t budget_bytes() const override { return budget_; }
+  int64_t max_tokens() const override { return mcap_; }
+  int64_t max_frames() const override { return fcap_; }
+  int rows_per_frame(int H, int W) const override { return (int)align_up((H / 14) * (W / 14) + 1, 8); }
+
+  uint64_t stream_bytes(const mf_stream_cfg& c, int ring_cap, int map_cap, int hist_n) const override {
+    const uint64_t hw = (uint64_t)c.height * c.width;
+    return (uint64_t)ring_cap * 3 * hw * 4 + (uint64_t)map_cap * hw * 4 + (uint64_t)hist_n * sizeof(FrameHist);
+  }
+
+  mf_status open_stream(const mf_stream_cfg& c, StreamRes* r, std::string& err) override {
+    HIPCHECK(hipSetDevice(device_));
+    const uint64_t hw = (uint64_t)c.height * c.width;
+    HIPCHECK(hipMalloc(&r->ring, (size_t)r->ring_cap * 3 * hw * 4));
+    if (r->map_cap > 0) HIPCHECK(hipMalloc(&r->maps, (size_t)r->map_cap * hw * 4));
+    HIPCHECK(hipMalloc(&r->hist, (size_t)r->hist_n * sizeof(FrameHist)));
+    HIPCHECK(hipMemsetAsync(r->hist, 0, (size_t)r->hist_n * sizeof(FrameHist), copy_));
+    HIPCHECK(hipMemsetAsync(r->ring, 0, (size_t)r->ring_cap * 3 * hw * 4, copy_));
+    HIPCHECK(hipStreamSynchronize(copy_));
+    return pe_rows_for(c.height / 14, c.width / 14, &r->pe_base, err);
+  }
+
+  void close_stream(StreamRes* r) override {
+    hipSetDevice(device_);
+    if (r->ring) hipFree(r->ring);
+    if (r->maps) hipFree(r->maps);
+    if (r->hist) hipFree(r->hist);
+    r->ring = r->maps = r->hist = nullptr;
+  }
+
+  mf_status upload_frames(const mf_stream_cfg& c, StreamRes* r, int64_t first, const float* src, int n,
+                          bool device_src, std::string& err) override {
+    HIPCHECK(hipSetDevice(device_));
+    const size_t fb = (size_t)3 * c.height * c.width * 4;
+    int done = 0;
+    while (done < n) {
+      const int64_t f = first + done;
+      const int slot = (int)(f % r->ring_cap);
+      const int run = std::min(n - done, r->ring_cap - slot);
+      HIPCHECK(hipMemcpyAsync((char*)r->ring + (size_t)slot * fb, (const char*)src + (size_t)done * fb,
+                              (size_t)run * fb, device_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              copy_));
+      done += run;
+    }
+    HIPCHECK(hipStreamSynchronize(copy_));
+    return MF_OK;
+  }
+
+  mf_status copy_maps(const mf_stream_cfg& c, StreamRes* r, int64_t frame, int n, float* dst, bool device_dst,
+                      std::string& err) override {
+    HIPCHECK(hipSetDevice(device_));
+    const size_t mb = (size_t)c.height * c.width * 4;
+    const int slot = (int)(frame % r->map_cap);
+    HIPCHECK(hipMemcpyAsync(dst, (char*)r->maps + (size_t)slot * mb, (size_t)n * mb,
+                            device_dst ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, copy_));
+    HIPCHECK(hipStreamSynchronize(copy_));
+    return MF_OK;
+  }
+
+  mf_status run_batch(const Batch& b, std::vector<mf_focus>& out, double* gpu_ms, std::string& err) override {
+    HIPCHECK(hipSetDevice(device_));
+    // ---- plan the forward part
+    Plan p;
+    std::vector<int32_t> loc_off(b.wins.size(), -1);
+    int32_t fwd_frames = 0;
+    for (size_t i = 0; i < b.wins.size(); ++i) {
+      const BatchWindow& w = b.wins[i];
+      if (w.poses) continue;
+      loc_off[i] = fwd_frames;
+      add_window(p, w);
+      fwd_frames += w.size;
+    }
+    int32_t pose_rows = 0;
+    for (size_t i = 0; i < b.wins.size(); ++i)
+      if (b.wins[i].poses) { loc_off[i] = fwd_frames + pose_rows; pose_rows += b.wins[i].size; }
+    if (p.mtot > mcap_ || fwd_frames + pose_rows > fcap_) { err = "batch exceeds the workspace"; return MF_EINVAL; }
+
+    // ---- chain / focus / map tables
+    std::vector<StreamDev> sdev;
+    std::vector<ChainGroup> groups;
+    std::vector<ChainWin> cwins;
+    std::vector<MapJob> jobs;
+    int32_t out_n = 0, max_h = 0, max_w = 0;
+    int32_t prev_stream = -1;
+    for (size_t i = 0; i < b.wins.size(); ++i) {
+      const BatchWindow& w = b.wins[i];
+      if (w.stream_id != prev_stream) {
+        StreamDev sd{};
+        sd.hist = (FrameHist*)w.res->hist;
+        sd.hist_mask = w.res->hist_n - 1;
+        sd.n_points = w.cfg->n_points;
+        sd.fx = w.cfg->fx; sd.fy = w.cfg->fy; sd.cx = w.cfg->cx; sd.cy = w.cfg->cy;
+        sd.sigma = w.cfg->sigma; sd.sigma_min = w.cfg->sigma_min; sd.sigma_max = w.cfg->sigma_max;
+        sd.anchor_mode = w.cfg->anchor_mode;
+        sd.H = w.cfg->height; sd.W = w.cfg->width;
+        sd.map_cap = w.res->map_cap;
+        sd.maps = (float*)w.res->maps;
+        sdev.push_back(sd);
+        groups.push_back({(int32_t)cwins.size(), 0});
+        prev_stream = w.stream_id;
+      }
+      ChainWin cw{};
+      cw.stream = (int32_t)sdev.size() - 1;
+      cw.mode = w.chain_mode;
+      cw.loc_off = loc_off[i];
+      cw.window_id = w.window_id;
+      cw.start = w.start;
+      cw.emit_begin = w.emit_begin;
+      cw.emit_end = w.emit_end;
+      cw.out_off = out_n;
+      cw.has_pose9 = w.poses ? 0 : 1;
+      cwins.push_back(cw);
+      groups.back().n_win++;
+      if (w.cfg->emit_maps) {
+        for (int64_t t = w.emit_begin; t < w.emit_end; ++t)
+          jobs.push_back({cw.stream, out_n + (int32_t)(t - w.emit_begin), t});
+        max_h = std::max(max_h, w.cfg->height);
+        max_w = std::max(max_w, w.cfg->width);
+      }
+      out_n += (int32_t)(w.emit_end - w.emit_begin);
+    }
+    if (out_n > fcap_ || (int64_t)jobs.size() > fcap_) { err = "batch emits more frames than the workspace holds"; return MF_EINVAL; }
+
+    // ---- pack every table into one pinned buffer, one upload
+    size_t off = 0;
+    auto reserve = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes, 256); return o; };
+    const size_t o_frames = reserve(p.frames.size() * sizeof(FrameDesc));
+    const size_t o_fsegs = reserve(p.fsegs.size() * sizeof(AttnSeg));
+    const size_t o_fwork = reserve(p.fwork.size() * sizeof(AttnWork));
+    const size_t o_gsegs = reserve(p.gsegs.size() * sizeof(AttnSeg));
+    const size_t o_gwork = reserve(p.gwork.size() * sizeof(AttnWork));
+    const size_t o_cam = reserve(p.cam_rows.size() * sizeof(int32_t));
+    const size_t o_sdev = reserve(sdev.size() * sizeof(StreamDev));
+    const size_t o_groups = reserve(groups.size() * sizeof(ChainGroup));
+    const size_t o_cwins = reserve(cwins.size() * sizeof(ChainWin));
+    const size_t o_jobs = reserve(jobs.size() * sizeof(MapJob));
+    const size_t o_poses = reserve((size_t)pose_rows * 16 * sizeof(double));
+    mf_status rc = ensure_tables(off, err);
+    if (rc != MF_OK) return rc;
+    auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) memcpy(tab_host_ + o, src, bytes); };
+    put(o_frames, p.frames.data(), p.frames.size() * sizeof(FrameDesc));
+    put(o_fsegs, p.fsegs.data(), p.fsegs.size() * sizeof(AttnSeg));
+    put(o_fwork, p.fwork.data(), p.fwork.size() * sizeof(AttnWork));
+    put(o_gsegs, p.gsegs.data(), p.gsegs.size() * sizeof(AttnSeg));
+    put(o_gwork, p.gwork.data(), p.gwork.size() * sizeof(AttnWork));
+    put(o_cam, p.cam_rows.data(), p.cam_rows.size() * sizeof(int32_t));
+    put(o_sdev, sdev.data(), sdev.size() * sizeof(StreamDev));
+    put(o_groups, groups.data(), groups.size() * sizeof(ChainGroup));
+    put(o_cwins, cwins.data(), cwins.size() * sizeof(ChainWin));
+    put(o_jobs, jobs.data(), jobs.size() * sizeof(MapJob));
+    {
+      size_t po = o_poses;
+      for (const BatchWindow& w : b.wins)
+        if (w.poses) { put(po, w.poses, (size_t)w.size * 16 * sizeof(double)); po += (size_t)w.size * 16 * sizeof(double); }
+    }
+    HIPCHECK(hipEventRecord(ev0_, st_));
+    HIPCHECK(hipMemcpyAsync(tab_dev_, tab_host_, off, hipMemcpyHostToDevice, st_));
+    auto T = [&](size_t o) { return (void*)(tab_dev_ + o); };
+
+    // ---- the network over every frame window of the batch
+    if (!p.frames.empty()) {
+      rc = forward(p, (const FrameDesc*)T(o_frames), (const AttnSeg*)T(o_fsegs), (const AttnWork*)T(o_fwork),
+                   (const AttnSeg*)T(o_gsegs), (const AttnWork*)T(o_gwork), (const int32_t*)T(o_cam),
+                   depth_, err);
+      if (rc != MF_OK) return rc;
+    }
+    if (pose_rows)
+      HIPCHECK(hipMemcpyAsync(tloc_ + (size_t)fwd_frames * 16, T(o_poses), (size_t)pose_rows * 16 * sizeof(double),
+                              hipMemcpyDeviceToDevice, st_));
+    HIPCHECK(chain_focus((const ChainGroup*)T(o_groups), (int)groups.size(), (const ChainWin*)T(o_cwins),
+                         (const StreamDev*)T(o_sdev), tloc_, pose9_, res_, st_));
+    HIPCHECK(focus_maps((const MapJob*)T(o_jobs), (int)jobs.size(), max_h, max_w, (const StreamDev*)T(o_sdev),
+                        res_, keys_, st_));
+    HIPCHECK(hipMemcpyAsync(res_host_, res_, (size_t)out_n * sizeof(mf_focus), hipMemcpyDeviceToHost, st_));
+    HIPCHECK(hipEventRecord(ev1_, st_));
+    HIPCHECK(hipStreamSynchronize(st_));
+    float ms = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&ms, ev0_, ev1_));
+    if (gpu_ms) *gpu_ms = ms;
+    collect_profile(err);
+    out.assign(res_host_, res_host_ + out_n);
+    return MF_OK;
+  }
+
+  mf_status forward_frames(const float* frames_dev, int S, int H, int W, float* pose9_host, double* T_host,
+                           int max_layers, float* tokens_host, std::string& err) override {
+    HIPCHECK(hipSetDevice(device_));
+    if (S < 1 || H % 14 || W % 14 || H <= 0 || W <= 0) { err = "bad frame geometry"; return MF_EINVAL; }
+    StreamRes r;
+    r.ring = (void*)frames_dev;
+    r.ring_cap = S;
+    mf_status rc = pe_rows_for(H / 14, W / 14, &r.pe_base, err);
+    if (rc != MF_OK) return rc;
+    mf_stream_cfg c{};
+    c.height = H;
+    c.width = W;
+    c.window = S;
+    BatchWindow w{};
+    w.cfg = &c;
+    w.res = &r;
+    w.start = 0;
+    w.size = S;
+    Plan p;
+    add_window(p, w);
+    if (p.mtot > mcap_) { err = "window exceeds the token workspace"; return MF_EINVAL; }
+    size_t off = 0;
+    auto reserve = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes, 256); return o; };
+    const size_t o_frames = reserve(p.frames.size() * sizeof(FrameDesc));
+    const size_t o_fsegs = reserve(p.fsegs.size() * sizeof(AttnSeg));
+    const size_t o_fwork = reserve(p.fwork.size() * sizeof(AttnWork));
+    const size_t o_gsegs = reserve(p.gsegs.size() * sizeof(AttnSeg));
+    const size_t o_gwork = reserve(p.gwork.size() * sizeof(AttnWork));
+    const size_t o_cam = reserve(p.cam_rows.size() * sizeof(int32_t));
+    rc = ensure_tables(off, err);
+    if (rc != MF_OK) return rc;
+    memcpy(tab_host_ + o_frames, p.frames.data(), p.frames.size() * sizeof(FrameDesc));
+    memcpy(tab_host_ + o_fsegs, p.fsegs.data(), p.fsegs.size() * sizeof(AttnSeg));
+    memcpy(tab_host_ + o_fwork, p.fwork.data(), p.fwork.size() * sizeof(AttnWork));
+    memcpy(tab_host_ + o_gsegs, p.gsegs.data(), p.gsegs.size() * sizeof(AttnSeg));
+    memcpy(tab_host_ + o_gwork, p.gwork.data(), p.gwork.size() * sizeof(AttnWork));
+    memcpy(tab_host_ + o_cam, p.cam_rows.data(), p.cam_rows.size() * sizeof(int32_t));
+    HIPCHECK(hipMemcpyAsync(tab_dev_, tab_host_, off, hipMemcpyHostToDevice, st_));
+    auto T = [&](size_t o) { return (void*)(tab_dev_ + o); };
+    const int layers = max_layers < 0 ? depth_ : std::min(max_layers, depth_);
+    rc = forward(p, (const FrameDesc*)T(o_frames), (const AttnSeg*)T(o_fsegs), (const AttnWork*)T(o_fwork),
+                 (const AttnSeg*)T(o_gsegs), (const AttnWork*)T(o_gwork), (const int32_t*)T(o_cam), layers, err);
+    if (rc != MF_OK) return rc;
+    if (pose9_host) HIPCHECK(hipMemcpyAsync(pose9_host, pose9_, (size_t)S * 9 * 4, hipMemcpyDeviceToHost, st_));
+    if (T_host) HIPCHECK(hipMemcpyAsync(T_host, tloc_, (size_t)S * 16 * 8, hipMemcpyDeviceToHost, st_));
+    if (tokens_host) HIPCHECK(hipMemcpyAsync(tokens_host, X_, (size_t)p.mtot * D_ * 4, hipMemcpyDeviceToHost, st_));
+    HIPCHECK(hipStreamSynchronize(st_));
+    collect_profile(err);
+    return MF_OK;
+  }
+
+  mf_status debug_copy(int which, void* host, size_t bytes, std::string& err) override {
+    HIPCHECK(hipSetDevice(device_));
+    const void* src[7] = {X_, Y_, Q_, K_, Vt_, O_, Hb_};
+    const size_t D = D_, wide = std::max<int64_t>(F_, KP);
+    const size_t cap[7] = {(size_t)mcap_ * D * 4, (size_t)mcap_ * D * es_, (size_t)mpad_ * D * es_,
+                           (size_t)mpad_ * D * es_, (size_t)mpad_ * D * es_, (size_t)mcap_ * D * es_,
+                           (size_t)mcap_ * wide * es_};
+    if (which < 0 || which > 6 || bytes > cap[which]) { err = "bad buffer or size"; return MF_EINVAL; }
+    HIPCHECK(hipStreamSynchronize(st_));
+    HIPCHECK(hipMemcpy(host, src[which], bytes, hipMemcpyDeviceToHost));
+    return MF_OK;
+  }
+
+  void profile(double* ag_ms, int64_t* ag_calls, double* af_ms, double* g_ms, int enable) override {
+    if (ag_ms) *ag_ms = prof_ag_ms_;
+    if (ag_calls) *ag_calls = prof_ag_calls_;
+    if (af_ms) *af_ms = prof_af_ms_;
+    if (g_ms) *g_ms = prof_gemm_ms_;
+    if (enable >= 0) {
+      profiling_ = enable != 0;
+      prof_ag_ms_ = prof_af_ms_ = prof_gemm_ms_ = 0.0;
+      prof_ag_calls_ = 0;
+    }
+  }
+
+ private:
+  // ------------------------------------------------------------------ sizes
+  size_t expected_floats() const {
+    const size_t D = D_, F = F_;
+    return 588 * D + 3 * D + depth_ * (2 * D + D * 3 * D + 3 * D + D * D + D + 2 * D + D * F + F + F * D + D) +
+           2 * D + D * D + D + D * 9 + 9;
+  }
+  uint64_t weight_bytes() const {
+    const uint64_t D = D_, F = F_;
+    return expected_floats() * 4 + (D * KP + depth_ * (3 * D * D + D * D + 2 * D * F)) * es_ + D * D * 4;
+  }
+  uint64_t workspace_bytes() const {
+    const uint64_t D = D_, wide = std::max<int64_t>(F_, KP);
+    return (uint64_t)mcap_ * (D * 4 + D * es_ + D * es_ + wide * es_ + 4) + (uint64_t)mpad_ * 3 * D * es_ +
+           (uint64_t)fcap_ * (2 * D * 4 + 9 * 4 + 16 * 8 + sizeof(mf_focus) * 2 + 8) + (64u << 20);
+  }
+
+  // ------------------------------------------------------------------ weights
+  mf_status load_weights(const float* w, size_t n, std::string& err) {
+    HIPCHECK(hipMalloc(&wdev_, n * 4));
+    HIPCHECK(hipMemcpy(wdev_, w, n * 4, hipMemcpyHostToDevice));
+    const float* p = wdev_;
+    auto take = [&](size_t cnt) { const float* q = p; p += cnt; return q; };
+    const size_t D = D_, F = F_;
+    const float* Wp = take(588 * D);
+    b_p_ = take(D); c_ref_ = take(D); c_other_ = take(D);
+    HIPCHECK(hipMalloc(&Wp_, D * KP * es_));
+    HIPCHECK(hipMemsetAsync(Wp_, 0, D * KP * es_, st_));
+    HIPCHECK(convert_transpose(dt_, Wp, 588, (int)D, Wp_, KP, st_));
+    layers_.resize(depth_);
+    for (int l = 0; l < depth_; ++l) {
+      LayerW& L = layers_[l];
+      L.ln1_g = take(D); L.ln1_b = take(D);
+      const float* Wqkv = take(D * 3 * D);
+      L.b_qkv = take(3 * D);
+      const float* Wo = take(D * D);
+      L.b_o = take(D);
+      L.ln2_g = take(D); L.ln2_b = take(D);
+      const float* W1 = take(D * F);
+      L.b_1 = take(F);
+      const float* W2 = take(F * D);
+      L.b_2 = take(D);
+      HIPCHECK(hipMalloc(&L.Wqkv, 3 * D * D * es_));
+      HIPCHECK(hipMalloc(&L.Wo, D * D * es_));
+      HIPCHECK(hipMalloc(&L.W1, D * F * es_));
+      HIPCHECK(hipMalloc(&L.W2, F * D * es_));
+      HIPCHECK(convert_transpose(dt_, Wqkv, (int)D, (int)(3 * D), L.Wqkv, (int)D, st_));
+      HIPCHECK(convert_transpose(dt_, Wo, (int)D, (int)D, L.Wo, (int)D, st_));
+      HIPCHECK(convert_transpose(dt_, W1, (int)D, (int)F, L.W1, (int)D, st_));
+      HIPCHECK(convert_transpose(dt_, W2, (int)F, (int)D, L.W2, (int)F, st_));
+    }
+    lnf_g_ = take(D); lnf_b_ = take(D);
+    const float* H1 = take(D * D);
+    h_1_ = take(D);
+    H_2_ = take(D * 9);
+    h_2_ = take(9);
+    HIPCHECK(hipMalloc(&H1t_, D * D * 4));
+    HIPCHECK(convert_transpose(DT_F32, H1, (int)D, (int)D, H1t_, (int)D, st_));
+    HIPCHECK(hipStreamSynchronize(st_));
+    return MF_OK;
+  }
+
+  mf_status alloc_workspace(std::string& err) {
+    const size_t D = D_, wide = std::max<int64_t>(F_, KP);
+    HIPCHECK(hipMalloc(&X_, (size_t)mcap_ * D * 4));
+    HIPCHECK(hipMalloc(&Y_, (size_t)mcap_ * D * es_));
+    HIPCHECK(hipMalloc(&O_, (size_t)mcap_ * D * es_));
+    HIPCHECK(hipMalloc(&Hb_, (size_t)mcap_ * wide * es_));
+    HIPCHECK(hipMalloc(&rowinfo_, (size_t)mcap_ * 4));
+    HIPCHECK(hipMalloc(&Q_, (size_t)mpad_ * D * es_));
+    HIPCHECK(hipMalloc(&K_, (size_t)mpad_ * D * es_));
+    HIPCHECK(hipMalloc(&Vt_, (size_t)mpad_ * D * es_));
+    // rows past the last token are read (masked) by attention tiles: keep them finite
+    HIPCHECK(hipMemsetAsync(Q_, 0, (size_t)mpad_ * D * es_, st_));
+    HIPCHECK(hipMemsetAsync(K_, 0, (size_t)mpad_ * D * es_, st_));
+    HIPCHECK(hipMemsetAsync(Vt_, 0, (size_t)mpad_ * D * es_, st_));
+    HIPCHECK(hipMemsetAsync(X_, 0, (size_t)mcap_ * D * 4, st_));
+    HIPCHECK(hipMemsetAsync(Y_, 0, (size_t)mcap_ * D * es_, st_));
+    HIPCHECK(hipMemsetAsync(O_, 0, (size_t)mcap_ * D * es_, st_));
+    HIPCHECK(hipStreamSynchronize(st_));
+    HIPCHECK(hipMalloc(&camln_, (size_t)fcap_ * D * 4));
+    HIPCHECK(hipMalloc(&camg_, (size_t)fcap_ * D * 4));
+    HIPCHECK(hipMalloc(&pose9_, (size_t)fcap_ * 9 * 4));
+    HIPCHECK(hipMalloc(&tloc_, (size_t)fcap_ * 16 * 8));
+    HIPCHECK(hipMalloc(&res_, (size_t)fcap_ * sizeof(mf_focus)));
+    HIPCHECK(hipMalloc(&keys_, (size_t)fcap_ * 8));
+    HIPCHECK(hipHostMalloc((void**)&res_host_, (size_t)fcap_ * sizeof(mf_focus), hipHostMallocDefault));
+    return MF_OK;
+  }
+
+  mf_status ensure_tables(size_t bytes, std::string& err) {
+    if (bytes <= tab_cap_) return MF_OK;
+    if (tab_dev_) HIPCHECK(hipFree(tab_dev_));
+    if (tab_host_) HIPCHECK(hipHostFree(tab_host_));
+    tab_cap_ = align_up(bytes * 2, 1 << 20);
+    HIPCHECK(hipMalloc((void**)&tab_dev_, tab_cap_));
+    HIPCHECK(hipHostMalloc((void**)&tab_host_, tab_cap_, hipHostMallocDefault));
+    return MF_OK;
+  }
+
+  // Position-code rows for a (gh, gw) grid: one table per resolution in a shared arena.
+  mf_status pe_rows_for(int gh, int gw, int* base, std::string& err) {
+    auto key = std::make_pair(gh, gw);
+    auto it = pe_index_.find(key);
+    if (it != pe_index_.end()) { *base = it->second; return MF_OK; }
+    if (!pe_) {
+      pe_cap_ = 32768;
+      HIPCHECK(hipMalloc(&pe_, (size_t)pe_cap_ * D_ * 4));
+    }
+    if (pe_rows_ + gh * gw > pe_cap_) { err = "too many distinct resolutions for the position-code arena"; return MF_ENOMEM; }
+    HIPCHECK(make_pe(pe_ + (size_t)pe_rows_ * D_, gh, gw, D_, copy_));
+    HIPCHECK(hipStreamSynchronize(copy_));
+    *base = pe_rows_;
+    pe_index_[key] = pe_rows_;
+    pe_rows_ += gh * gw;
+    return MF_OK;
+  }
+
+  // ------------------------------------------------------------------ batch planning
+  void add_window(Plan& p, const BatchWindow& w) const {
+    const int H = w.cfg->height, W = w.cfg->width, gw = W / 14, P = (H / 14) * gw;
+    const int n = P + 1, npad = rows_per_frame(H, W);
+    const size_t fb = (size_t)3 * H * W;
+    const int32_t base = (int32_t)p.mtot;
+    for (int j = 0; j < w.size; ++j) {
+      FrameDesc fd;
+      const int64_t f = w.start + j;
+      fd.px = (const float*)w.res->ring + (size_t)(f % w.res->ring_cap) * fb;
+      fd.H = H; fd.W = W; fd.gw = gw; fd.P = P;
+      fd.token_base = base + j * npad;
+      fd.npad = npad;
+      fd.first = j == 0;
+      fd.pe_base = w.res->pe_base;
+      p.frames.push_back(fd);
+      p.cam_rows.push_back(fd.token_base);
+      const int32_t si = (int32_t)p.fsegs.size();
+      p.fsegs.push_back({fd.token_base, 1, n, npad});
+      for (int q0 = 0; q0 < n; q0 += QT) p.fwork.push_back({si, q0});
+    }
+    const int32_t gi = (int32_t)p.gsegs.size();
+    p.gsegs.push_back({base, w.size, n, npad});
+    for (int q0 = 0; q0 < w.size * npad; q0 += QT) p.gwork.push_back({gi, q0});
+    p.mtot += (int64_t)w.size * npad;
+    p.max_npad = std::max(p.max_npad, npad);
+  }
+
+  // ------------------------------------------------------------------ the network
+  mf_status forward(const Plan& p, const FrameDesc* frames, const AttnSeg* fsegs, const AttnWork* fwork,
+                    const AttnSeg* gsegs, const AttnWork* gwork, const int32_t* cam_rows, int layers,
+                    std::string& err) {
+    const int M = (int)p.mtot, D = D_;
+    HIPCHECK(im2col(dt_, frames, (int)p.frames.size(), p.max_npad, Hb_, KP, rowinfo_, st_));
+    GemmArgs g{};
+    g.A = Hb_; g.lda = KP; g.Bt = Wp_; g.ldb = KP; g.M = M; g.N = D; g.K = KP;
+    g.bias = b_p_; g.C = X_; g.ldc = D; g.N = D;
+    g.rowinfo = rowinfo_; g.pe = pe_; g.c_ref = c_ref_; g.c_other = c_other_;
+    HIPCHECK(run_gemm(EPI_PATCH, g));
+    for (int l = 0; l < layers; ++l) {
+      const LayerW& L = layers_[l];
+      HIPCHECK(layernorm(dt_, X_, Y_, L.ln1_g, L.ln1_b, M, D, nullptr, st_));
+      GemmArgs q{};
+      q.A = Y_; q.lda = D; q.Bt = L.Wqkv; q.ldb = D; q.M = M; q.N = 3 * D; q.K = D; q.bias = L.b_qkv;
+      q.q = Q_; q.k = K_; q.vt = Vt_; q.heads = H_; q.hd = hd_; q.mpad = mpad_;
+      HIPCHECK(run_gemm(EPI_QKV, q));
+      const bool global = (l % 2) == 1;
+      prof_begin();
+      if (global)
+        HIPCHECK(attention(dt_, hd_, Q_, K_, Vt_, O_, mpad_, H_, D, gsegs, gwork, (int)p.gwork.size(), st_));
+      else
+        HIPCHECK(attention(dt_, hd_, Q_, K_, Vt_, O_, mpad_, H_, D, fsegs, fwork, (int)p.fwork.size(), st_));
+      prof_end(global ? 1 : 2);
+      GemmArgs o{};
+      o.A = O_; o.lda = D; o.Bt = L.Wo; o.ldb = D; o.M = M; o.N = D; o.K = D; o.bias = L.b_o; o.C = X_; o.ldc = D;
+      HIPCHECK(run_gemm(EPI_RESID, o));
+      HIPCHECK(layernorm(dt_, X_, Y_, L.ln2_g, L.ln2_b, M, D, nullptr, st_));
+      GemmArgs f1{};
+      f1.A = Y_; f1.lda = D; f1.Bt = L.W1; f1.ldb = D; f1.M = M; f1.N = F_; f1.K = D; f1.bias = L.b_1;
+      f1.C = Hb_; f1.ldc = F_;
+      HIPCHECK(run_gemm(EPI_GELU, f1));
+      GemmArgs f2{};
+      f2.A = Hb_; f2.lda = F_; f2.Bt = L.W2; f2.ldb = F_; f2.M = M; f2.N = D; f2.K = F_; f2.bias = L.b_2;
+      f2.C = X_; f2.ldc = D;
+      HIPCHECK(run_gemm(EPI_RESID, f2));
+    }
+    if (layers == depth_) {
+      const int Fr = (int)p.frames.size();
+      HIPCHECK(layernorm(DT_F32, X_, camln_, lnf_g_, lnf_b_, Fr, D, cam_rows, st_));
+      GemmArgs h{};
+      h.A = camln_; h.lda = D; h.Bt = H1t_; h.ldb = D; h.M = Fr; h.N = D; h.K = D; h.bias = h_1_;
+      h.C = camg_; h.ldc = D;
+      HIPCHECK(gemm(DT_F32, EPI_GELU, h, st_));
+      HIPCHECK(pose_out(camg_, H_2_, h_2_, Fr, D, pose9_, tloc_, st_));
+    }
+    return MF_OK;
+  }
+
+  hipError_t run_gemm(Epi e, const GemmArgs& a) {
+    prof_begin();
+    const hipError_t r = gemm(dt_, e, a, st_);
+    prof_end(3);
+    return r;
+  }
+
+  // ------------------------------------------------------------------ optional per-kernel timing
+  struct ProfEv { hipEvent_t a, b; int kind; };
+  std::vector<ProfEv> prof_pool_;
+  size_t prof_used_ = 0;
+  void prof_begin() {
+    if (!profiling_) return;
+    if (prof_used_ == prof_pool_.size()) {
+      ProfEv e;
+      hipEventCreate(&e.a);
+      hipEventCreate(&e.b);
+      prof_pool_.push_back(e);
+    }
+    hipEventRecord(prof_pool_[prof_used_].a, st_);
+  }
+  void prof_end(int kind) {
+    if (!profiling_) return;
+    hipEventRecord(prof_pool_[prof_used_].b, st_);
+    prof_pool_[prof_used_].kind = kind;
+    prof_used_++;
+  }
+  void collect_profile(std::string&) {
+    for (size_t i = 0; i < prof_used_; ++i) {
+      float ms = 0.0f;
+      hipEventSynchronize(prof_pool_[i].b);
+      hipEventElapsedTime(&ms, prof_pool_[i].a, prof_pool_[i].b);
+      if (prof_pool_[i].kind == 1) { prof_ag_ms_ += ms; prof_ag_calls_++; }
+      else if (prof_pool_[i].kind == 2) prof_af_ms_ += ms;
+      else prof_gemm_ms_ += ms;
+    }
+    prof_used_ = 0;
+  }
+
+  void release() {
+    hipSetDevice(device_);
+    auto F = [](void* p) { if (p) hipFree(p); };
+    F(wdev_); F(Wp_); F(H1t_);
+    for (auto& L : layers_) { F(L.Wqkv); F(L.Wo); F(L.W1); F(L.W2); }
+    F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(Q_); F(K_); F(Vt_);
+    F(camln_); F(camg_); F(pose9_); F(tloc_); F(res_); F(keys_); F(pe_); F(tab_dev_);
+    if (res_host_) hipHostFree(res_host_);
+    if (tab_host_) hipHostFree(tab_host_);
+    for (auto& e : prof_pool_) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
+    if (ev0_) hipEventDestroy(ev0_);
+    if (ev1_) hipEventDestroy(ev1_);
+    if (copy_) hipStreamDestroy(copy_);
+    if (own_stream_ && st_) hipStreamDestroy(st_);
+  }
+
+  mf_model_cfg m_{};
+  int D_ = 0, H_ = 0, hd_ = 0, F_ = 0, depth_ = 0, device_ = 0;
+  Dtype dt_ = DT_F32;
+  size_t es_ = 4;
+  hipStream_t st_ = nullptr, copy_ = nullptr;
+  bool own_stream_ = false;
+  uint64_t budget_ = 0;
+  int64_t mcap_ = 0, mpad_ = 0, fcap_ = 0;
+  float* wdev_ = nullptr;
+  const float *b_p_ = nullptr, *c_ref_ = nullptr, *c_other_ = nullptr, *lnf_g_ = nullptr, *lnf_b_ = nullptr;
+  const float *h_1_ = nullptr, *H_2_ = nullptr, *h_2_ = nullptr;
+  void* Wp_ = nullptr;
+  float* H1t_ = nullptr;
+  std::vector<LayerW> layers_;
+  float* X_ = nullptr;
+  void *Y_ = nullptr, *O_ = nullptr, *Hb_ = nullptr, *Q_ = nullptr, *K_ = nullptr, *Vt_ = nullptr;
+  int32_t* rowinfo_ = nullptr;
+  float *camln_ = nullptr, *camg_ = nullptr, *pose9_ = nullptr;
+  double* tloc_ = nullptr;
+  mf_focus* res_ = nullptr;
+  mf_focus* res_host_ = nullptr;
+  unsigned long long* keys_ = nullptr;
+  char* tab_dev_ = nullptr;
+  char* tab_host_ = nullptr;
+  size_t tab_cap_ = 0;
+  float* pe_ = nullptr;
+  int pe_rows_ = 0, pe_cap_ = 0;
+  std::map<std::pair<int, int>, int> pe_index_;
+  hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+  bool profiling_ = false;
+  double prof_ag_ms_ = 0, prof_af_ms_ = 0, prof_gemm_ms_ = 0;
+  int64_t prof_ag_calls_ = 0;
+};
+
+Executor* make_executor() { return new HipExecutor(); }
+
+}  // namespace mf

@@ -1,0 +1,215 @@
+// MFMA GEMM for gfx950 with fused epilogues: C = A Bt^T + bias, then store / += residual /
+// erf-GELU / scatter into head-major Q, K and transposed V / patch-embedding assembly.
+//
+// Workgroup: 256 threads = 2 x 2 waves; each wave owns a (32 WM) x (32 WN) block of 32x32
+// MFMA tiles.  A and Bt tiles are staged through LDS in 128-byte k-slices (64 bf16 or
+// 32 fp32 per row), double-buffered, with the 16-byte chunks of each row XOR-swizzled by the
+// row index so that the per-lane 16-byte fragment reads are conflict free.
+//   bf16: v_mfma_f32_32x32x16_bf16, one 16-byte fragment (8 k) per lane per MFMA
+//   fp32: v_mfma_f32_32x32x2_f32, the same 16-byte fragment feeds 4 MFMAs
+// A and B use the same (lane group, register) -> k assignment, so the contraction is
+// over every k exactly once whatever order the hardware sums in.
+#include "device.h"
+#include "kernels.h"
+
+namespace mf {
+
+template <typename T> struct Mma;
+template <> struct Mma<bf16> {
+  static MF_DEV void run(const uint4& a, const uint4& b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&a, *(const bf16x8*)&b, c, 0, 0, 0);
+  }
+};
+template <> struct Mma<float> {
+  static MF_DEV void run(const uint4& a, const uint4& b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  }
+};
+
+// EPI_QKV: n is the column within the q, k or v block (qkv_which 0, 1, 2) and dst that block.
+template <typename T, int EPI>
+MF_DEV void epilogue(const GemmArgs& a, int m, int n, float v, int qkv_which = 0, T* dst = nullptr) {
+  if (a.bias && EPI != EPI_PATCH && EPI != EPI_QKV) v += a.bias[n];
+  if constexpr (EPI == EPI_RESID) {
+    float* c = (float*)a.C + (int64_t)m * a.ldc + n;
+    *c += v;
+  } else if constexpr (EPI == EPI_GELU) {
+    ((T*)a.C)[(int64_t)m * a.ldc + n] = from_f32<T>(gelu_erf(v));
+  } else if constexpr (EPI == EPI_STORE) {
+    ((T*)a.C)[(int64_t)m * a.ldc + n] = from_f32<T>(v);
+  } else if constexpr (EPI == EPI_QKV) {
+    // which (q, k or v) is uniform over the tile: the caller passes it resolved, with dst
+    const int h = n / a.hd, d = n - h * a.hd;
+    if (qkv_which < 2)
+      dst[((int64_t)h * a.mpad + m) * a.hd + d] = from_f32<T>(v);
+    else
+      dst[((int64_t)h * a.hd + d) * a.mpad + m] = from_f32<T>(v);
+  } else if constexpr (EPI == EPI_PATCH) {
+    // rowinfo: bits 30-31 kind (0 patch, 1 reference camera, 2 other camera, 3 gap), low bits PE row
+    const int32_t ri = a.rowinfo[m];
+    const int kind = (ri >> 30) & 3;
+    float out;
+    if (kind == 0) out = v + a.bias[n] + a.pe[(int64_t)(ri & 0x3fffffff) * a.N + n];
+    else if (kind == 1) out = a.c_ref[n];
+    else if (kind == 2) out = a.c_other[n];
+    else out = 0.0f;
+    ((float*)a.C)[(int64_t)m * a.ldc + n] = out;
+  }
+}
+
+template <typename T, int WM, int WN, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
+  constexpr int BM = 64 * WM, BN = 64 * WN;
+  constexpr int EPC = 16 / sizeof(T);   // elements per 16-byte chunk
+  constexpr int BK = 8 * EPC;           // elements per 128-byte row slice
+  constexpr int ACH = BM * 8 / 256, BCH = BN * 8 / 256;   // chunks per thread
+  __shared__ uint4 sA[2][BM * 8];
+  __shared__ uint4 sB[2][BN * 8];
+
+  const int tilesN = a.N / BN;
+  const int tilesM = (a.M + BM - 1) / BM;
+  const int nb = tilesM * tilesN;
+  const int bid = xcd_remap(blockIdx.x, nb);
+  const int tm = bid / tilesN, tn = bid - tm * tilesN;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int g = lane >> 5, l32 = lane & 31;
+
+  const T* A = (const T*)a.A;
+  const T* B = (const T*)a.Bt;
+  const T* aptr[ACH];
+  const T* bptr[BCH];
+  int aoff[ACH], boff[BCH];
+#pragma unroll
+  for (int i = 0; i < ACH; ++i) {
+    const int c = tid + i * 256, row = c >> 3, col = c & 7;
+    const int gm = min(m0 + row, a.M - 1);
+    aptr[i] = A + (int64_t)gm * a.lda + col * EPC;
+    aoff[i] = row * 8 + (col ^ (row & 7));
+  }
+#pragma unroll
+  for (int i = 0; i < BCH; ++i) {
+    const int c = tid + i * 256, row = c >> 3, col = c & 7;
+    bptr[i] = B + (int64_t)(n0 + row) * a.ldb + col * EPC;
+    boff[i] = row * 8 + (col ^ (row & 7));
+  }
+
+  f32x16 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  uint4 ra[ACH], rb[BCH];
+#pragma unroll
+  for (int i = 0; i < ACH; ++i) ra[i] = *(const uint4*)aptr[i];
+#pragma unroll
+  for (int i = 0; i < BCH; ++i) rb[i] = *(const uint4*)bptr[i];
+#pragma unroll
+  for (int i = 0; i < ACH; ++i) sA[0][aoff[i]] = ra[i];
+#pragma unroll
+  for (int i = 0; i < BCH; ++i) sB[0][boff[i]] = rb[i];
+  __syncthreads();
+
+  const int nk = a.K / BK;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) {
+#pragma unroll
+      for (int i = 0; i < ACH; ++i) ra[i] = *(const uint4*)(aptr[i] + (int64_t)(kt + 1) * BK);
+#pragma unroll
+      for (int i = 0; i < BCH; ++i) rb[i] = *(const uint4*)(bptr[i] + (int64_t)(kt + 1) * BK);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      uint4 fa[WM], fb[WN];
+      const int ch = 2 * kk + g;
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const int row = wr * 32 * WM + i * 32 + l32;
+        fa[i] = sA[cur][row * 8 + (ch ^ (row & 7))];
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int row = wc * 32 * WN + j * 32 + l32;
+        fb[j] = sB[cur][row * 8 + (ch ^ (row & 7))];
+      }
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) Mma<T>::run(fa[i], fb[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) {
+#pragma unroll
+      for (int i = 0; i < ACH; ++i) sA[cur ^ 1][aoff[i]] = ra[i];
+#pragma unroll
+      for (int i = 0; i < BCH; ++i) sB[cur ^ 1][boff[i]] = rb[i];
+    }
+    __syncthreads();
+  }
+
+  // The q / k / v block of a QKV tile is uniform (the block width D is a multiple of BN):
+  // resolve it once per workgroup.
+  int which = 0, nbase = 0;
+  T* dst = nullptr;
+  if constexpr (EPI == EPI_QKV) {
+    const int D = a.heads * a.hd;
+    which = n0 / D;
+    nbase = which * D;
+    dst = (T*)(which == 0 ? a.q : (which == 1 ? a.k : a.vt));
+  }
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int n = n0 + wc * 32 * WN + j * 32 + l32;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wr * 32 * WM + i * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
+        if (m < a.M) {
+          if constexpr (EPI == EPI_QKV) {
+            const float v = acc[i][j][r] + a.bias[n];
+            epilogue<T, EPI>(a, m, n - nbase, v, which, dst);
+          } else {
+            epilogue<T, EPI>(a, m, n, acc[i][j][r]);
+          }
+        }
+      }
+    }
+}
+
+template <typename T, int EPI>
+static hipError_t launch(const GemmArgs& a, hipStream_t s) {
+  constexpr int WM = 2, WN = 2, BM = 64 * WM, BN = 64 * WN;
+  constexpr int BK = 128 / sizeof(T);
+  if (a.M <= 0) return hipSuccess;
+  if (a.N % BN != 0 || a.K % BK != 0 || a.K <= 0) return hipErrorInvalidValue;
+  if (EPI == EPI_QKV && ((a.heads * a.hd) % BN != 0 || !a.bias)) return hipErrorInvalidValue;
+  const int nb = ((a.M + BM - 1) / BM) * (a.N / BN);
+  hipLaunchKernelGGL((gemm_kernel<T, WM, WN, EPI>), dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t dispatch(Epi epi, const GemmArgs& a, hipStream_t s) {
+  switch (epi) {
+    case EPI_RESID: return launch<T, EPI_RESID>(a, s);
+    case EPI_GELU: return launch<T, EPI_GELU>(a, s);
+    case EPI_QKV: return launch<T, EPI_QKV>(a, s);
+    case EPI_PATCH: return launch<T, EPI_PATCH>(a, s);
+    case EPI_STORE: return launch<T, EPI_STORE>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t gemm(Dtype dt, Epi epi, const GemmArgs& a, hipStream_t s) {
+  return dt == DT_BF16 ? dispatch<bf16>(epi, a, s) : dispatch<float>(epi, a, s);
+}
+
+}  // namespace mf

@@ -1,0 +1,102 @@
+// Host-side launchers of the gfx950 kernels (internal interface of the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mf {
+
+enum Dtype { DT_F32 = 0, DT_BF16 = 1 };
+
+// ---------------------------------------------------------------- GEMM  C = A Bt^T (+ epilogue)
+enum Epi { EPI_RESID = 1, EPI_GELU = 2, EPI_QKV = 3, EPI_PATCH = 4, EPI_STORE = 5 };
+
+struct GemmArgs {
+  const void* A; int64_t lda;      // [M, K] row-major, dtype
+  const void* Bt; int64_t ldb;     // [N, K] row-major (the weight transposed), dtype
+  int M, N, K;                     // K a multiple of the k-tile (64 bf16 / 32 fp32)
+  const float* bias;               // [N] or null
+  void* C; int64_t ldc;            // RESID: fp32 [M,N] (+=); GELU/STORE: dtype [M,N]; PATCH: fp32 X
+  // EPI_QKV: Q, K head-major [H][mpad][hd], V transposed [H][hd][mpad]
+  void* q; void* k; void* vt; int heads; int hd; int64_t mpad;
+  // EPI_PATCH: per-row kind/PE row (rowinfo), PE table [rows][N] fp32, camera tokens
+  const int32_t* rowinfo; const float* pe; const float* c_ref; const float* c_other;
+};
+hipError_t gemm(Dtype dt, Epi epi, const GemmArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- attention over segments
+struct AttnSeg { int32_t base, nf, n, npad; };   // tokens [base, base+nf*npad); frame stride npad, n valid
+struct AttnWork { int32_t seg, q0; };             // a 128-query tile of a segment
+hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void* vt, void* o,
+                     int64_t mpad, int heads, int dim, const AttnSeg* segs, const AttnWork* work,
+                     int nwork, hipStream_t s);
+
+// ---------------------------------------------------------------- LayerNorm (fp32 in, dtype out)
+// rows: optional gather table (out row i <- in row rows[i]).
+hipError_t layernorm(Dtype out_dt, const float* x, void* y, const float* g, const float* b,
+                     int64_t nrows, int dim, const int32_t* rows, hipStream_t s);
+
+// ---------------------------------------------------------------- patch embedding input
+struct FrameDesc {
+  const float* px;        // [3, H, W] fp32 pixels in [0,1)
+  int32_t H, W, gw, P;    // grid width, patches
+  int32_t token_base;     // row of the frame's camera token
+  int32_t npad;           // rows reserved for the frame
+  int32_t first;          // 1 for the first frame of its window (reference camera token)
+  int32_t pe_base;        // first row of the frame's resolution in the PE arena
+};
+// Writes the normalised patch matrix A [rows, kpad] (dtype) and rowinfo for every token row.
+hipError_t im2col(Dtype dt, const FrameDesc* frames, int nframes, int max_npad, void* A, int kpad,
+                  int32_t* rowinfo, hipStream_t s);
+hipError_t make_pe(float* pe, int gh, int gw, int dim, hipStream_t s);
+
+// ---------------------------------------------------------------- weights
+// out[c * ld_out + r] = w[r * cols + c]
+hipError_t convert_transpose(Dtype dt, const float* w, int rows, int cols, void* out, int ld_out,
+                             hipStream_t s);
+
+// ---------------------------------------------------------------- pose head tail
+// g: [F, D] fp32 (after Linear-GELU), H2: [D, 9] fp32, h2: [9] -> pose9 [F, 9] fp32, T_loc [F,16] fp64
+hipError_t pose_out(const float* g, const float* H2, const float* h2, int F, int dim, float* pose9,
+                    double* T_loc, hipStream_t s);
+
+}  // namespace mf
+
+// ---------------------------------------------------------------- chaining, focus and maps (FP64)
+#include "../../include/mf.h"
+namespace mf {
+
+struct FrameHist {            // per-stream device history entry (ring indexed by frame & mask)
+  double T[16];               // world-to-camera pose
+  double a_w[3];              // world acceleration (Eq. 3)
+  double s;                   // |a_w|
+  int32_t valid;              // focus point defined
+  int32_t pad;
+};
+
+struct StreamDev {            // per-stream constants of one batch
+  FrameHist* hist; int32_t hist_mask; int32_t n_points;
+  double fx, fy, cx, cy, sigma, sigma_min, sigma_max;
+  int32_t anchor_mode, H, W, map_cap;
+  float* maps;                // map ring [map_cap][H][W]
+};
+
+enum ChainMode { CHAIN_ANCHOR = 0, CHAIN_FIRST = 1, CHAIN_WORLD = 2 };
+
+struct ChainWin {             // one window of one stream in this batch
+  int32_t stream, mode, loc_off, window_id;
+  int64_t start, emit_begin, emit_end;
+  int32_t out_off, has_pose9;
+};
+struct ChainGroup { int32_t first_win, n_win; };   // the windows of one stream, in order
+
+struct MapJob { int32_t stream, out; int64_t frame; };
+
+// T_loc [rows][16] fp64 local poses, pose9 [rows][9] (nullable); out: result records.
+hipError_t chain_focus(const ChainGroup* groups, int ngroups, const ChainWin* wins,
+                       const StreamDev* streams, const double* T_loc, const float* pose9,
+                       mf_focus* out, hipStream_t s);
+// keys: [njobs] scratch (cleared here).  Renders every job's map into its stream's ring.
+hipError_t focus_maps(const MapJob* jobs, int njobs, int max_h, int max_w, const StreamDev* streams,
+                      mf_focus* out, unsigned long long* keys, hipStream_t s);
+
+}  // namespace mf

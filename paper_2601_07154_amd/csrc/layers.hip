@@ -1,0 +1,200 @@
+// Row-wise kernels: LayerNorm, patch extraction with ImageNet normalisation, the 2-D sin-cos
+// position table, weight conversion, and the tail of the camera-token pose head.
+#include "device.h"
+#include "kernels.h"
+
+namespace mf {
+
+// ------------------------------------------------------------------ LayerNorm, one wave per row
+// (x - mean) / sqrt(var + 1e-6) * g + b with fp32 statistics (two passes over registers).
+template <typename T, int VPL>
+__global__ __launch_bounds__(256) void ln_kernel(const float* __restrict__ x, T* __restrict__ y,
+                                                 const float* __restrict__ g,
+                                                 const float* __restrict__ b, int64_t nrows,
+                                                 const int32_t* __restrict__ rows) {
+  constexpr int D = VPL * 64;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= nrows) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t src = rows ? rows[r] : r;
+  const float* xr = x + src * D;
+  float v[VPL];
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) v[i] = xr[i * 64 + lane];
+  float s = 0.0f;
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) s += v[i];
+  const float mean = wave_sum(s) * (1.0f / D);
+  float q = 0.0f;
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) {
+    const float d = v[i] - mean;
+    q += d * d;
+  }
+  const float rstd = rsqrtf(wave_sum(q) * (1.0f / D) + 1e-6f);
+  T* yr = y + r * D;
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) {
+    const int c = i * 64 + lane;
+    yr[c] = from_f32<T>((v[i] - mean) * rstd * g[c] + b[c]);
+  }
+}
+
+template <typename T>
+static hipError_t ln_launch(const float* x, void* y, const float* g, const float* b,
+                            int64_t nrows, int dim, const int32_t* rows, hipStream_t s) {
+  const dim3 grid((unsigned)((nrows + 3) / 4));
+  switch (dim) {
+    case 128: hipLaunchKernelGGL((ln_kernel<T, 2>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
+    case 256: hipLaunchKernelGGL((ln_kernel<T, 4>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
+    case 384: hipLaunchKernelGGL((ln_kernel<T, 6>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
+    case 512: hipLaunchKernelGGL((ln_kernel<T, 8>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
+    case 768: hipLaunchKernelGGL((ln_kernel<T, 12>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
+    case 1024: hipLaunchKernelGGL((ln_kernel<T, 16>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t layernorm(Dtype out_dt, const float* x, void* y, const float* g, const float* b,
+                     int64_t nrows, int dim, const int32_t* rows, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  return out_dt == DT_BF16 ? ln_launch<bf16>(x, y, g, b, nrows, dim, rows, s)
+                           : ln_launch<float>(x, y, g, b, nrows, dim, rows, s);
+}
+
+// ------------------------------------------------------------------ patch matrix
+// Block (x, f): token rows x*4 .. x*4+3 of frame f (one wave per row).  Row kinds: the
+// camera token (row 0), patches (rows 1..P, grid row-major) and padding (P+1 .. npad-1).
+// A patch row holds (pixel - mean_c) / std_c flattened (c, ky, kx), zero beyond 588.
+template <typename T>
+__global__ __launch_bounds__(256) void im2col_kernel(const FrameDesc* __restrict__ frames,
+                                                     T* __restrict__ A, int kpad,
+                                                     int32_t* __restrict__ rowinfo) {
+  const FrameDesc fd = frames[blockIdx.y];
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= fd.npad) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)fd.token_base + j;
+  T* ar = A + row * kpad;
+  if (j == 0 || j > fd.P) {
+    for (int k = lane; k < kpad; k += 64) ar[k] = from_f32<T>(0.0f);
+    if (lane == 0) rowinfo[row] = j == 0 ? (fd.first ? (1 << 30) : (2 << 30)) : (3 << 30);
+    return;
+  }
+  const int p = j - 1;
+  const int py = p / fd.gw, px = p - py * fd.gw;
+  const float mean[3] = {0.485f, 0.456f, 0.406f};
+  const float istd[3] = {1.0f / 0.229f, 1.0f / 0.224f, 1.0f / 0.225f};
+  for (int k = lane; k < kpad; k += 64) {
+    float v = 0.0f;
+    if (k < 588) {
+      const int c = k / 196, rem = k - c * 196, ky = rem / 14, kx = rem - ky * 14;
+      const float pix = fd.px[((int64_t)c * fd.H + py * 14 + ky) * fd.W + px * 14 + kx];
+      v = (pix - mean[c]) * istd[c];
+    }
+    ar[k] = from_f32<T>(v);
+  }
+  if (lane == 0) rowinfo[row] = fd.pe_base + p;
+}
+
+hipError_t im2col(Dtype dt, const FrameDesc* frames, int nframes, int max_npad, void* A, int kpad,
+                  int32_t* rowinfo, hipStream_t s) {
+  if (nframes <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((max_npad + 3) / 4), (unsigned)nframes);
+  if (dt == DT_BF16)
+    hipLaunchKernelGGL((im2col_kernel<bf16>), grid, dim3(256), 0, s, frames, (bf16*)A, kpad, rowinfo);
+  else
+    hipLaunchKernelGGL((im2col_kernel<float>), grid, dim3(256), 0, s, frames, (float*)A, kpad, rowinfo);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ sin-cos position table
+// pe[y*gw + x][c]: c in quarter 0..3 -> sin(y w), cos(y w), sin(x w), cos(x w),
+// w_i = 10000^(-i/(dim/4)); evaluated in double, stored fp32.
+__global__ void pe_kernel(float* pe, int gh, int gw, int dim) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)gh * gw * dim) return;
+  const int c = (int)(idx % dim);
+  const int p = (int)(idx / dim);
+  const int y = p / gw, x = p - y * gw;
+  const int q = dim / 4, quarter = c / q, i = c - quarter * q;
+  const double w = pow(10000.0, -(double)i / q);
+  const double arg = (quarter < 2 ? y : x) * w;
+  pe[idx] = (float)((quarter & 1) ? cos(arg) : sin(arg));
+}
+
+hipError_t make_pe(float* pe, int gh, int gw, int dim, hipStream_t s) {
+  const int64_t n = (int64_t)gh * gw * dim;
+  hipLaunchKernelGGL(pe_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pe, gh, gw, dim);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ weights: [rows, cols] fp32 -> [cols, rows] dtype
+template <typename T>
+__global__ void transpose_kernel(const float* __restrict__ w, int rows, int cols, T* __restrict__ out,
+                                 int ld_out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)rows * cols) return;
+  const int r = (int)(idx / cols), c = (int)(idx % cols);
+  out[(int64_t)c * ld_out + r] = from_f32<T>(w[idx]);
+}
+
+hipError_t convert_transpose(Dtype dt, const float* w, int rows, int cols, void* out, int ld_out,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)rows * cols;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (dt == DT_BF16)
+    hipLaunchKernelGGL((transpose_kernel<bf16>), grid, dim3(256), 0, s, w, rows, cols, (bf16*)out, ld_out);
+  else
+    hipLaunchKernelGGL((transpose_kernel<float>), grid, dim3(256), 0, s, w, rows, cols, (float*)out, ld_out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ pose head tail
+// One wave per frame: o = g H2 + h2 (fp32), then the world-to-camera pose [R(q) | t] in double:
+// q = o[3:7] (x, y, z, w) normalised (identity below 1e-12), t = o[0:3].
+__global__ __launch_bounds__(64) void pose_out_kernel(const float* __restrict__ g,
+                                                      const float* __restrict__ H2,
+                                                      const float* __restrict__ h2, int dim,
+                                                      float* __restrict__ pose9,
+                                                      double* __restrict__ T_loc) {
+  const int f = blockIdx.x, lane = threadIdx.x;
+  const float* gr = g + (int64_t)f * dim;
+  float acc[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) acc[j] = 0.0f;
+  for (int c = lane; c < dim; c += 64) {
+    const float v = gr[c];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc[j] = fmaf(v, H2[c * 9 + j], acc[j]);
+  }
+  float o[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) o[j] = wave_sum(acc[j]) + h2[j];
+  if (lane != 0) return;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) pose9[f * 9 + j] = o[j];
+  double x = o[3], y = o[4], z = o[5], w = o[6];
+  const double nrm = sqrt(x * x + y * y + z * z + w * w);
+  double* T = T_loc + (int64_t)f * 16;
+  if (nrm < 1e-12) {
+    x = y = z = 0.0;
+    w = 1.0;
+  } else {
+    x /= nrm; y /= nrm; z /= nrm; w /= nrm;
+  }
+  T[0] = 1 - 2 * (y * y + z * z); T[1] = 2 * (x * y - z * w);     T[2] = 2 * (x * z + y * w);     T[3] = o[0];
+  T[4] = 2 * (x * y + z * w);     T[5] = 1 - 2 * (x * x + z * z); T[6] = 2 * (y * z - x * w);     T[7] = o[1];
+  T[8] = 2 * (x * z - y * w);     T[9] = 2 * (y * z + x * w);     T[10] = 1 - 2 * (x * x + y * y); T[11] = o[2];
+  T[12] = 0; T[13] = 0; T[14] = 0; T[15] = 1;
+}
+
+hipError_t pose_out(const float* g, const float* H2, const float* h2, int F, int dim, float* pose9,
+                    double* T_loc, hipStream_t s) {
+  if (F <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pose_out_kernel, dim3(F), dim3(64), 0, s, g, H2, h2, dim, pose9, T_loc);
+  return hipGetLastError();
+}
+
+}  // namespace mf

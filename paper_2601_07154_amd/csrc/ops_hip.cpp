@@ -1,0 +1,76 @@
+// Single-stage entry points (attention, GEMM, LayerNorm) over caller-provided device buffers.
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mf_ops.h"
+#include "kernels.h"
+
+using namespace mf;
+
+extern "C" {
+
+int32_t mf_rows_per_frame(int32_t height, int32_t width) {
+  const int32_t n = (height / 14) * (width / 14) + 1;
+  return (n + 7) / 8 * 8;
+}
+
+mf_status mf_op_attention(int32_t precision, int32_t head_dim, int32_t heads, int32_t dim, const void* q,
+                          const void* k, const void* vt, void* o, int64_t mpad, const int32_t* segs, int32_t nseg,
+                          void* stream) {
+  if (!q || !k || !vt || !o || !segs || nseg < 1 || heads < 1 || heads * head_dim != dim) return MF_EINVAL;
+  if (head_dim != 32 && head_dim != 64) return MF_EINVAL;
+  std::vector<AttnSeg> sg(nseg);
+  std::vector<AttnWork> wk;
+  for (int i = 0; i < nseg; ++i) {
+    sg[i] = {segs[4 * i], segs[4 * i + 1], segs[4 * i + 2], segs[4 * i + 3]};
+    const AttnSeg& s = sg[i];
+    if (s.base < 0 || s.nf < 1 || s.n < 1 || s.npad < s.n || s.npad % 8 || s.base % 8) return MF_EINVAL;
+    const int64_t end = (int64_t)s.base + (int64_t)s.nf * s.npad;
+    if (end + 256 > mpad) return MF_EINVAL;
+    const int qend = s.nf == 1 ? s.n : s.nf * s.npad;
+    for (int q0 = 0; q0 < qend; q0 += 128) wk.push_back({i, q0});
+  }
+  hipStream_t st = (hipStream_t)stream;
+  void* dev = nullptr;
+  const size_t sb = sg.size() * sizeof(AttnSeg), wb = wk.size() * sizeof(AttnWork);
+  if (hipMalloc(&dev, sb + wb) != hipSuccess) return MF_EDEVICE;
+  hipMemcpyAsync(dev, sg.data(), sb, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync((char*)dev + sb, wk.data(), wb, hipMemcpyHostToDevice, st);
+  hipError_t r = attention(precision == MF_BF16 ? DT_BF16 : DT_F32, head_dim, q, k, vt, o, mpad, heads, dim,
+                           (const AttnSeg*)dev, (const AttnWork*)((char*)dev + sb), (int)wk.size(), st);
+  hipStreamSynchronize(st);
+  hipFree(dev);
+  return r == hipSuccess ? MF_OK : MF_EDEVICE;
+}
+
+mf_status mf_op_gemm(int32_t precision, const void* A, const void* Bt, const float* bias, float* C, int32_t M,
+                     int32_t N, int32_t K, void* stream) {
+  if (!A || !Bt || !C || M < 0 || N % 128 || K <= 0) return MF_EINVAL;
+  if (K % (precision == MF_BF16 ? 64 : 32)) return MF_EINVAL;
+  GemmArgs a{};
+  a.A = A; a.lda = K; a.Bt = Bt; a.ldb = K; a.M = M; a.N = N; a.K = K; a.bias = bias; a.C = C; a.ldc = N;
+  // fp32 output: the STORE epilogue of the fp32 instantiation writes float; for bf16 operands
+  // the accumulator is stored through the residual epilogue onto a zeroed C.
+  hipError_t r;
+  if (precision == MF_BF16) {
+    r = hipMemsetAsync(C, 0, (size_t)M * N * 4, (hipStream_t)stream);
+    if (r == hipSuccess) r = gemm(DT_BF16, EPI_RESID, a, (hipStream_t)stream);
+  } else {
+    r = gemm(DT_F32, EPI_STORE, a, (hipStream_t)stream);
+  }
+  if (r == hipSuccess) r = hipStreamSynchronize((hipStream_t)stream);
+  return r == hipSuccess ? MF_OK : MF_EDEVICE;
+}
+
+mf_status mf_op_layernorm(int32_t precision, const float* x, void* y, const float* g, const float* b, int64_t rows,
+                          int32_t dim, void* stream) {
+  if (!x || !y || !g || !b || rows < 0) return MF_EINVAL;
+  hipError_t r = layernorm(precision == MF_BF16 ? DT_BF16 : DT_F32, x, y, g, b, rows, dim, nullptr,
+                           (hipStream_t)stream);
+  if (r == hipSuccess) r = hipStreamSynchronize((hipStream_t)stream);
+  return r == hipSuccess ? MF_OK : MF_EDEVICE;
+}
+
+}  // extern "C"

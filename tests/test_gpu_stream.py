@@ -1,0 +1,137 @@
+"""End-to-end parity through the stream C ABI: push frames (or poses) -> windows -> forward ->
+anchoring -> focus -> maps, against the oracle pipeline."""
+import math
+
+import numpy as np
+import pytest
+
+import mf_synth
+from gpu_util import mf, torch_cuda
+from oracle import motion, pipeline, vit
+
+pytestmark = pytest.mark.gpu
+
+
+def _drain(eng, sid, H, W, cap=4096):
+    recs, maps = [], []
+    while True:
+        buf = np.zeros((cap, H, W), np.float32)
+        r, st = eng.poll(sid, cap, buf)
+        if len(r):
+            recs.append(r)
+            maps.append(buf[:len(r)])
+        if st != 0:
+            break
+    return np.concatenate(recs), np.concatenate(maps)
+
+
+def _run_poses_engine(m, T, K, H, W, sigma, n_points=15, local_windows=None):
+    eng = m.Engine(1, 128, 4, 128, np.zeros(mf_synth.weight_count(mf_synth.ModelConfig(1, 128, 4, 128)),
+                                            np.float32), precision="fp32", max_tokens=16384)
+    n = len(T) if T is not None else sum(len(t) for _, t in local_windows)
+    sid = eng.open_stream(H, W, 16, 8, K, n_points=n_points, sigma=sigma, result_frames=max(64, n))
+    if local_windows is None:
+        eng.push_poses(sid, T, 0, eos=True)
+    else:
+        for (start, Tl) in local_windows:
+            eng.push_poses(sid, Tl, start, local=True)
+        eng.close_stream(sid)
+    eng.sync()
+    recs, maps = _drain(eng, sid, H, W)
+    eng.close()
+    return recs, maps
+
+
+def test_world_poses_closed_form_head_yaw():
+    """Forward acceleration with the head turned by psi: u = cx - fx tan(psi), v = cy."""
+    torch_cuda()
+    m = mf()
+    K = (400.0, 400.0, 252.0, 140.0)
+    psi = 12.0
+    path = mf_synth.CameraPath(velocity=(0, 0, 1.0), accel=(0, 0, 0.8), sway_deg=0.0, yaw0_deg=psi)
+    T = path.poses(40)
+    recs, maps = _run_poses_engine(m, T, K, 280, 504, sigma=2e4)
+    assert list(recs["frame"]) == list(range(40))
+    assert not recs["valid"][:2].any() and (recs["valid"][2:] & 1).all()
+    np.testing.assert_allclose(recs["u"][2:], K[2] - K[0] * math.tan(math.radians(psi)), rtol=1e-9)
+    np.testing.assert_allclose(recs["v"][2:], K[3], atol=1e-9)
+
+
+def test_world_poses_match_oracle_track_and_maps():
+    torch_cuda()
+    m = mf()
+    K = (400.0, 380.0, 252.0, 140.0)
+    H, W = 140, 252
+    path = mf_synth.CameraPath(velocity=(0.2, 0.0, 1.5), accel=(0.3, -0.1, 0.5), sway_deg=3.0)
+    T = path.poses(50)
+    sigma = 3e4
+    recs, maps = _run_poses_engine(m, T, K, H, W, sigma)
+    ref = pipeline.run_poses(T, K, H, W, sigma=sigma)
+    tr = ref["track"]
+    np.testing.assert_array_equal(recs["valid"] & 1, tr["valid"].astype(np.int32))
+    v = tr["valid"]
+    np.testing.assert_allclose(recs["a_world"], tr["a_w"], rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(recs["a_cam"], tr["a_c"], rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(recs["u"][v], tr["uv"][v, 0], rtol=1e-9)
+    np.testing.assert_allclose(recs["v"][v], tr["uv"][v, 1], rtol=1e-9)
+    np.testing.assert_allclose(maps, ref["maps"], atol=1e-5)
+    for i, r in enumerate(recs):
+        if ref["Z"][i] >= 1e-30:
+            assert r["valid"] & 2
+            am = r["peak_y"] * W + r["peak_x"]
+            assert ref["maps"][i].ravel()[am] >= 1.0 - 1e-5
+        else:
+            assert not (r["valid"] & 2) and not maps[i].any()
+
+
+def test_local_poses_anchoring_matches_oracle():
+    """Window-local poses (arbitrary yaw-plus-shift frames per window) chained by the library in
+    FP64 reproduce the oracle's chaining exactly (and the true trajectory)."""
+    torch_cuda()
+    m = mf()
+    rng = np.random.default_rng(11)
+    N, L, O = 48, 16, 8
+    path = mf_synth.CameraPath(velocity=(0.1, 0, 1.2), accel=(0, 0.05, 0.4), sway_deg=4.0)
+    T_w = path.poses(N)
+    sched = motion.window_schedule(N, L, O)
+    wins, locs = [], []
+    for k, w in enumerate(sched):
+        G = np.eye(4)
+        if k:
+            G[:3, :3] = mf_synth.rot_y(rng.uniform(-2, 2))
+            G[:3, 3] = rng.uniform(-3, 3, 3)
+        Tl = np.stack([T_w[t] @ np.linalg.inv(G) for t in range(w["start"], w["start"] + w["size"])])
+        wins.append((w["start"], Tl))
+        locs.append(Tl)
+    K = (400.0, 400.0, 126.0, 70.0)
+    recs, _ = _run_poses_engine(m, None, K, 140, 252, 1e4, local_windows=wins)
+    chained = motion.chain_windows(sched, locs, motion.ANCHOR_YAW)
+    got = recs["T_w2c"].reshape(-1, 4, 4)
+    np.testing.assert_allclose(got, chained, atol=1e-12)
+    np.testing.assert_allclose(got, T_w, atol=1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_tiny_stream_end_to_end(prec):
+    torch = torch_cuda()
+    m = mf()
+    wl = mf_synth.TINY
+    blob = mf_synth.make_weights(wl.model, wl.seed_weights)
+    frames = mf_synth.workload_frames(wl)
+    K = (wl.fx, wl.fy, wl.cx, wl.cy)
+    eng = m.Engine.from_model(wl.model, blob, precision=prec, max_tokens=4096)
+    sid = eng.open_stream(wl.height, wl.width, wl.window, wl.overlap, K, sigma=50.0)
+    eng.push_frames(sid, torch.from_numpy(frames).cuda(), eos=True)
+    eng.sync()
+    recs, maps = _drain(eng, sid, wl.height, wl.width)
+    w = vit.unpack_weights(blob, wl.model.depth, wl.model.dim, wl.model.mlp)
+    ref = pipeline.run_stream(frames, w, wl.model.heads, wl.window, wl.overlap, K, sigma=50.0)
+    assert list(recs["frame"]) == list(range(wl.frames))
+    got_T = recs["T_w2c"].reshape(-1, 4, 4)
+    err_T = np.abs(got_T - ref["T_w"]).max()
+    print(f"{prec}: max |T - T_ref| = {err_T:.3e}")
+    if prec == "fp32":
+        assert err_T < 1e-4
+        np.testing.assert_array_equal(recs["valid"] & 1, ref["track"]["valid"].astype(np.int32))
+    else:
+        assert err_T < 0.05
