@@ -18,16 +18,16 @@ PRECISIONS = {"fp32": MF_FP32, "bf16": MF_BF16}
 
 
 class MfError(RuntimeError):
-    def __init__(self, status: int, where: str):
-        lib = _lib.lib()
+    def __init__(self, status: int, where: str, lib=None):
+        lib = lib or _lib.lib()
         msg = lib.mf_last_error().decode(errors="replace")
         super().__init__(f"{where}: {lib.mf_status_str(status).decode()} ({status}): {msg}")
         self.status = status
 
 
-def _check(status: int, where: str, ok=(MF_OK,)):
+def _check(status: int, where: str, ok=(MF_OK,), lib=None):
     if status not in ok:
-        raise MfError(status, where)
+        raise MfError(status, where, lib)
     return status
 
 
@@ -51,15 +51,15 @@ class Engine:
 
     def __init__(self, depth: int, dim: int, heads: int, mlp: int, weights: np.ndarray,
                  precision: str = "bf16", threaded: bool = False, max_tokens: int = 0,
-                 hbm_budget: int = 0, device: int = 0, stream: int | None = None):
-        self.lib = _lib.lib()
+                 hbm_budget: int = 0, device: int = 0, stream: int | None = None, lib=None):
+        self.lib = lib or _lib.lib()
         w = np.ascontiguousarray(weights, dtype=np.float32)
         m = _lib.ModelCfg(depth, dim, heads, mlp, 14, PRECISIONS[precision])
         rt = _lib.RuntimeCfg(device, 1 if threaded else 0, max_tokens, hbm_budget,
                              C.c_void_p(stream) if stream else None)
         h = C.c_void_p()
         _check(self.lib.mf_engine_create(C.byref(m), C.c_void_p(w.ctypes.data), w.size, C.byref(rt),
-                                         C.byref(h)), "mf_engine_create")
+                                         C.byref(h)), "mf_engine_create", lib=self.lib)
         self.h = h
         self.dim = dim
         self.precision = precision
@@ -98,7 +98,7 @@ class Engine:
         st = self.lib.mf_open_stream(self.h, C.byref(c), C.byref(sid))
         if allow_again and st == MF_EAGAIN:
             return -1
-        _check(st, "mf_open_stream")
+        _check(st, "mf_open_stream", lib=self.lib)
         return sid.value
 
     def push_frames(self, sid: int, frames, eos: bool = False, allow_again: bool = False) -> int:
@@ -111,16 +111,16 @@ class Engine:
             p, dev = _ptr(frames)
         flags = (MF_EOS if eos else 0) | (MF_DEVICE_PTR if dev else 0)
         st = self.lib.mf_push_frames(self.h, sid, p, n, flags)
-        return _check(st, "mf_push_frames", (MF_OK, MF_EAGAIN) if allow_again else (MF_OK,))
+        return _check(st, "mf_push_frames", (MF_OK, MF_EAGAIN) if allow_again else (MF_OK,), lib=self.lib)
 
     def push_poses(self, sid: int, T, first_frame: int, local: bool = False, eos: bool = False) -> int:
         T = np.ascontiguousarray(T, dtype=np.float64).reshape(-1, 16)
         flags = (MF_EOS if eos else 0) | (MF_POSES_LOCAL if local else 0)
         return _check(self.lib.mf_push_poses(self.h, sid, C.c_void_p(T.ctypes.data), T.shape[0], first_frame,
-                                             flags), "mf_push_poses")
+                                             flags), "mf_push_poses", lib=self.lib)
 
     def close_stream(self, sid: int):
-        _check(self.lib.mf_close_stream(self.h, sid), "mf_close_stream")
+        _check(self.lib.mf_close_stream(self.h, sid), "mf_close_stream", lib=self.lib)
 
     def poll(self, sid: int, cap: int = 4096, maps=None):
         """Returns (records [n] FOCUS_DTYPE, status) with status MF_OK, MF_EAGAIN or MF_ECLOSED."""
@@ -129,20 +129,20 @@ class Engine:
         mp, mdev = (None, False) if maps is None else _ptr(maps)
         st = self.lib.mf_poll_focus(self.h, sid, C.c_void_p(out.ctypes.data), cap, C.byref(n), mp,
                                     MF_DEVICE_PTR if mdev else 0)
-        _check(st, "mf_poll_focus", (MF_OK, MF_EAGAIN, MF_ECLOSED))
+        _check(st, "mf_poll_focus", (MF_OK, MF_EAGAIN, MF_ECLOSED), lib=self.lib)
         return out[:n.value].copy(), st
 
     def step(self) -> int:
         n = C.c_int32()
-        _check(self.lib.mf_engine_step(self.h, C.byref(n)), "mf_engine_step")
+        _check(self.lib.mf_engine_step(self.h, C.byref(n)), "mf_engine_step", lib=self.lib)
         return n.value
 
     def sync(self):
-        _check(self.lib.mf_engine_sync(self.h), "mf_engine_sync")
+        _check(self.lib.mf_engine_sync(self.h), "mf_engine_sync", lib=self.lib)
 
     def stats(self) -> dict:
         s = _lib.Stats()
-        _check(self.lib.mf_engine_stats(self.h, C.byref(s)), "mf_engine_stats")
+        _check(self.lib.mf_engine_stats(self.h, C.byref(s)), "mf_engine_stats", lib=self.lib)
         return {f: getattr(s, f) for f, _ in _lib.Stats._fields_}
 
     # ---------------------------------------------------------------- op level
@@ -158,19 +158,19 @@ class Engine:
         _check(self.lib.mf_forward_window(self.h, p, S, H, W, max_layers, C.c_void_p(pose9.ctypes.data),
                                           C.c_void_p(T.ctypes.data),
                                           C.c_void_p(tok.ctypes.data) if tok is not None else None),
-               "mf_forward_window")
+               "mf_forward_window", lib=self.lib)
         return pose9, T, tok
 
     def debug_copy(self, which: int, shape, dtype) -> np.ndarray:
         out = np.zeros(shape, dtype=dtype)
-        _check(self.lib.mf_debug_copy(self.h, which, C.c_void_p(out.ctypes.data), out.nbytes), "mf_debug_copy")
+        _check(self.lib.mf_debug_copy(self.h, which, C.c_void_p(out.ctypes.data), out.nbytes), "mf_debug_copy", lib=self.lib)
         return out
 
     def profile(self, enable: int = -1) -> dict:
         ag, af, gm = C.c_double(), C.c_double(), C.c_double()
         calls = C.c_int64()
         _check(self.lib.mf_profile(self.h, enable, C.byref(ag), C.byref(calls), C.byref(af), C.byref(gm)),
-               "mf_profile")
+               "mf_profile", lib=self.lib)
         return dict(attn_global_ms=ag.value, attn_global_calls=calls.value, attn_frame_ms=af.value,
                     gemm_ms=gm.value)
 

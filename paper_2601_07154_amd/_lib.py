@@ -97,9 +97,12 @@ EXPORTS = {
 }
 
 
-def bind(path: str):
+def bind(path: str, strict: bool = True):
+    """Load a library and declare the prototypes of EXPORTS (strict: every one must exist)."""
     lib = C.CDLL(path)
     for name, (res, args) in EXPORTS.items():
+        if not strict and not hasattr(lib, name):
+            continue
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args

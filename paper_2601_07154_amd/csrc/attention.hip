@@ -170,14 +170,14 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
     // mask keys outside the segment or in the padding rows between frames
     const int f0 = kt / sg.npad;
     const bool full = kt + BK <= (f0 * sg.npad + sg.n) && kt + BK <= key_end;
-    if (!full) {
+    if (!full) {   // branch-free select: no divergent control flow around the scores
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int key = kt + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-          const bool ok = key < key_end && (key % sg.npad) < sg.n;
-          if (!ok) s[kb][r] = -INFINITY;
+          const unsigned key = (unsigned)(kt + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3));
+          const bool ok = (key < (unsigned)key_end) & ((key % (unsigned)sg.npad) < (unsigned)sg.n);
+          s[kb][r] = ok ? s[kb][r] : -INFINITY;
         }
     }
     float mx = -INFINITY;
@@ -239,6 +239,213 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
   }
 }
 
+
+// ------------------------------------------------------------------ bf16, hd = 64, 64 queries/wave
+// Each wave owns two 32-query blocks that share every K and V^T fragment read from LDS (half
+// the LDS traffic per flop of one block per wave); a workgroup covers 256 queries.  The running
+// max is only moved when some lane's tile max exceeds it by more than 2^8 (the probabilities
+// then stay <= 256, exact in fp32 and representable in bf16), so the O rescale and its
+// accumulator traffic are rare.  Row sums are taken from the bf16-rounded probabilities that
+// the PV product uses (v_dot2), so numerator and denominator see the same weights.
+namespace v2 {
+constexpr int HD = 64, BK = 64, QW = 64, QT = 256;
+constexpr int CPR = 8;   // 16-byte chunks per 128-byte row (K rows: 64 d; V^T rows: 64 keys)
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+MF_DEV float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+__global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict__ Q, const bf16* __restrict__ K,
+                                                         const bf16* __restrict__ Vt, bf16* __restrict__ O,
+                                                         int64_t mpad, int heads, int dim,
+                                                         const AttnSeg* __restrict__ segs,
+                                                         const AttnWork* __restrict__ work, int nwork,
+                                                         float c) {
+  __shared__ uint4 sK[2][BK * CPR];
+  __shared__ uint4 sV[2][HD * CPR];
+  const int nb = nwork * heads;
+  const int bid = xcd_remap(blockIdx.x, nb);
+  const int h = bid % heads, wi = bid / heads;
+  const AttnWork wk = work[wi];
+  const AttnSeg sg = segs[wk.seg];
+  const int seg_len = sg.nf * sg.npad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 5, l32 = lane & 31;
+  const int qbase = wk.q0 + wave * QW;            // this wave's first query (segment-relative)
+
+  const bf16* Qh = Q + ((int64_t)h * mpad + sg.base) * HD;
+  const bf16* Kh = K + ((int64_t)h * mpad + sg.base) * HD;
+  const bf16* Vh = Vt + (int64_t)h * HD * mpad + sg.base;
+
+  uint4 qf[2][4];
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb) {
+    const uint4* qr = (const uint4*)(Qh + (int64_t)(qbase + hb * 32 + l32) * HD);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) qf[hb][f] = qr[2 * f + g];
+  }
+
+  uint4 rk[2], rv[2];
+  auto load_tile = [&](int kt) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ch = tid + i * 256, row = ch >> 3, col = ch & 7;
+      rk[i] = *(const uint4*)(Kh + (int64_t)(kt + row) * HD + col * 8);
+      rv[i] = *(const uint4*)(Vh + (int64_t)row * mpad + kt + col * 8);
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ch = tid + i * 256, row = ch >> 3, col = ch & 7;
+      sK[buf][row * CPR + (col ^ (row & 7))] = rk[i];
+      sV[buf][row * CPR + (col ^ (row & 7))] = rv[i];
+    }
+  };
+
+  f32x16 o[2][2];
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[hb][t][r] = 0.0f;
+  float m_run[2] = {-INFINITY, -INFINITY}, l_run[2] = {0.0f, 0.0f};
+
+  const int key_end = sg.nf == 1 ? sg.n : seg_len;
+  const int ntiles = (key_end + BK - 1) / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  const bf16x2_t ones = {(bf16)1.0f, (bf16)1.0f};
+
+  for (int it = 0; it < ntiles; ++it) {
+    const int cur = it & 1, kt = it * BK;
+    if (it + 1 < ntiles) load_tile(kt + BK);
+
+    // S^T for 64 keys x (2 x 32) queries; K fragments shared by both query blocks
+    f32x16 s[2][2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const int krow = kb * 32 + l32;
+      uint4 kf[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) kf[f] = sK[cur][krow * CPR + ((2 * f + g) ^ (krow & 7))];
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s[hb][kb][r] = 0.0f;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+          s[hb][kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf[f], *(const bf16x8*)&qf[hb][f],
+                                                               s[hb][kb], 0, 0, 0);
+      }
+    }
+    const int f0 = kt / sg.npad;
+    const bool full = kt + BK <= (f0 * sg.npad + sg.n) && kt + BK <= key_end;
+    if (!full) {   // branch-free select: no divergent control flow around the scores
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const unsigned key = (unsigned)(kt + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3));
+          const bool ok = (key < (unsigned)key_end) & ((key % (unsigned)sg.npad) < (unsigned)sg.n);
+          s[0][kb][r] = ok ? s[0][kb][r] : -INFINITY;
+          s[1][kb][r] = ok ? s[1][kb][r] : -INFINITY;
+        }
+    }
+    // running max: moved only when a tile max exceeds it by more than 8 (log2 units)
+    float mx[2];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      float a = s[hb][0][0];
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) a = fmaxf(a, s[hb][kb][r]);
+      a = fmaxf(a, __shfl_xor(a, 32, 64));
+      mx[hb] = a * c;
+    }
+    const bool grow = (mx[0] > m_run[0] + 8.0f) || (mx[1] > m_run[1] + 8.0f);
+    if (__any(grow)) {
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb) {
+        const float m_new = fmaxf(m_run[hb], mx[hb]);
+        const float alpha = m_new == -INFINITY ? 1.0f : fast_exp2(m_run[hb] - m_new);
+        m_run[hb] = m_new;
+        l_run[hb] *= alpha;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) o[hb][t][r] *= alpha;
+      }
+    }
+    // probabilities (bf16, B operand of PV) and their row sums
+    bf16x8 pf[2][2][2];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      const float nm = -m_run[hb];
+      float ls = 0.0f;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int j2 = 0; j2 < 2; ++j2) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) pf[hb][kb][j2][r] = (bf16)fast_exp2(fmaf(s[hb][kb][8 * j2 + r], c, nm));
+#pragma unroll
+          for (int r = 0; r < 8; r += 2) {
+            const bf16x2_t pr = {pf[hb][kb][j2][r], pf[hb][kb][j2][r + 1]};
+            ls = __builtin_amdgcn_fdot2_f32_bf16(pr, ones, ls, false);
+          }
+        }
+      l_run[hb] += ls;
+    }
+    // O^T += V^T P^T; V fragments shared by both query blocks
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int drow = t * 32 + l32;
+      const int sw = drow & 7;
+      const uint2* row = (const uint2*)(sV[cur] + drow * CPR);
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int j2 = 0; j2 < 2; ++j2) {
+          const int c0 = 4 * kb + 2 * j2;
+          const uint2 lo = row[2 * (c0 ^ sw) + g];
+          const uint2 hi = row[2 * ((c0 + 1) ^ sw) + g];
+          const uint4 vf = {lo.x, lo.y, hi.x, hi.y};
+#pragma unroll
+          for (int hb = 0; hb < 2; ++hb)
+            o[hb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&vf, pf[hb][kb][j2], o[hb][t], 0, 0, 0);
+        }
+    }
+    if (it + 1 < ntiles) {
+      __syncthreads();
+      store_tile(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb) {
+    const int qrow = qbase + hb * 32 + l32;
+    const float l_tot = l_run[hb] + __shfl_xor(l_run[hb], 32, 64);
+    const float inv = 1.0f / l_tot;
+    if (qrow < seg_len) {
+      bf16* orow = O + (int64_t)(sg.base + qrow) * dim + h * HD;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bf16x4 v;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = (bf16)(o[hb][t][4 * j + i] * inv);
+          *(bf16x4*)(orow + t * 32 + 8 * j + 4 * g) = v;
+        }
+    }
+  }
+}
+}  // namespace v2
+
 template <typename T, int HD>
 static hipError_t launch(const void* q, const void* k, const void* vt, void* o, int64_t mpad,
                          int heads, int dim, const AttnSeg* segs, const AttnWork* work, int nwork,
@@ -251,11 +458,19 @@ static hipError_t launch(const void* q, const void* k, const void* vt, void* o, 
   return hipGetLastError();
 }
 
+int attention_q_tile(Dtype dt, int hd) { return (dt == DT_BF16 && hd == 64) ? v2::QT : 128; }
+
 hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void* vt, void* o,
                      int64_t mpad, int heads, int dim, const AttnSeg* segs, const AttnWork* work,
                      int nwork, hipStream_t s) {
   if (dt == DT_BF16) {
-    if (hd == 64) return launch<bf16, 64>(q, k, vt, o, mpad, heads, dim, segs, work, nwork, s);
+    if (hd == 64) {
+      if (nwork <= 0) return hipSuccess;
+      const float c = (float)(1.4426950408889634 / 8.0);
+      hipLaunchKernelGGL(v2::attn_kernel_v2, dim3(nwork * heads), dim3(256), 0, s, (const bf16*)q, (const bf16*)k,
+                         (const bf16*)vt, (bf16*)o, mpad, heads, dim, segs, work, nwork, c);
+      return hipGetLastError();
+    }
     if (hd == 32) return launch<bf16, 32>(q, k, vt, o, mpad, heads, dim, segs, work, nwork, s);
   } else {
     if (hd == 64) return launch<float, 64>(q, k, vt, o, mpad, heads, dim, segs, work, nwork, s);

@@ -428,12 +428,10 @@ mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream
             (long long)rows, (long long)e->ex->max_tokens());
     return MF_EINVAL;
   }
-  // history ring: every frame one batch can emit for this stream, plus the N points and the
-  // window that the maps and the anchor look back on
-  const int64_t per_batch = std::max<int64_t>(e->ex->max_tokens() / e->ex->rows_per_frame(c.height, c.width),
-                                              (int64_t)c.window * 64);
+  // history ring: the frames one batch may emit for this stream (at least 8 windows' worth),
+  // plus the N points and the window that the maps and the anchor look back on
   int hist_n = 64;
-  while (hist_n < std::min<int64_t>(per_batch, e->ex->max_frames()) + c.n_points + c.window + 8) hist_n *= 2;
+  while (hist_n < std::max(8 * c.window, 256) + c.n_points + c.window + 8) hist_n *= 2;
   const uint64_t need = e->ex->stream_bytes(c, c.ring_frames, c.emit_maps ? c.result_frames : 0, hist_n);
   auto s = std::make_shared<Stream>();
   {
@@ -590,8 +588,9 @@ mf_status mf_push_poses(mf_engine* e, int32_t stream_id, const double* T, int32_
         set_err("world poses must continue the stream at frame %lld", (long long)s->emitted_end);
         return MF_EINVAL;
       }
-      if (n > s->cfg.window * 64) {
-        set_err("push at most %d world poses per call", s->cfg.window * 64);
+      const int span = s->res.hist_n - s->cfg.n_points - s->cfg.window - 8;
+      if (n > span) {
+        set_err("push at most %d world poses per call", span);
         return MF_EINVAL;
       }
       j.mode = CHAIN_WORLD_;

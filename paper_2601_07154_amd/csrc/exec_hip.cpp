@@ -25,7 +25,6 @@ namespace mf {
   } while (0)
 
 static constexpr int KP = 640;     // patch length 3*14*14 = 588 padded to the GEMM k-tile
-static constexpr int QT = 128;     // queries per attention workgroup
 
 static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -59,6 +58,7 @@ class HipExecutor : public Executor {
     if (F_ <= 0 || F_ % 128) { err = "mlp must be a positive multiple of 128"; return MF_EINVAL; }
     dt_ = m.precision == MF_BF16 ? DT_BF16 : DT_F32;
     es_ = dt_ == DT_BF16 ? 2 : 4;
+    qt_ = attention_q_tile(dt_, hd_);
     const size_t want = expected_floats();
     if (n != want) { err = "weight blob has " + std::to_string(n) + " floats, the model needs " + std::to_string(want); return MF_EINVAL; }
     HIPCHECK(hipSetDevice(rt.device));
@@ -484,11 +484,11 @@ class HipExecutor : public Executor {
       p.cam_rows.push_back(fd.token_base);
       const int32_t si = (int32_t)p.fsegs.size();
       p.fsegs.push_back({fd.token_base, 1, n, npad});
-      for (int q0 = 0; q0 < n; q0 += QT) p.fwork.push_back({si, q0});
+      for (int q0 = 0; q0 < n; q0 += qt_) p.fwork.push_back({si, q0});
     }
     const int32_t gi = (int32_t)p.gsegs.size();
     p.gsegs.push_back({base, w.size, n, npad});
-    for (int q0 = 0; q0 < w.size * npad; q0 += QT) p.gwork.push_back({gi, q0});
+    for (int q0 = 0; q0 < w.size * npad; q0 += qt_) p.gwork.push_back({gi, q0});
     p.mtot += (int64_t)w.size * npad;
     p.max_npad = std::max(p.max_npad, npad);
   }
@@ -599,7 +599,7 @@ class HipExecutor : public Executor {
   }
 
   mf_model_cfg m_{};
-  int D_ = 0, H_ = 0, hd_ = 0, F_ = 0, depth_ = 0, device_ = 0;
+  int D_ = 0, H_ = 0, hd_ = 0, F_ = 0, depth_ = 0, device_ = 0, qt_ = 128;
   Dtype dt_ = DT_F32;
   size_t es_ = 4;
   hipStream_t st_ = nullptr, copy_ = nullptr;

@@ -61,13 +61,14 @@ MF_DEV void epilogue(const GemmArgs& a, int m, int n, float v, int qkv_which = 0
 }
 
 template <typename T, int WM, int WN, int EPI>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
+__global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   constexpr int BM = 64 * WM, BN = 64 * WN;
   constexpr int EPC = 16 / sizeof(T);   // elements per 16-byte chunk
   constexpr int BK = 8 * EPC;           // elements per 128-byte row slice
   constexpr int ACH = BM * 8 / 256, BCH = BN * 8 / 256;   // chunks per thread
-  __shared__ uint4 sA[2][BM * 8];
-  __shared__ uint4 sB[2][BN * 8];
+  // one LDS stage: the next k-slice is prefetched into registers while this one is consumed
+  __shared__ uint4 sA[BM * 8];
+  __shared__ uint4 sB[BN * 8];
 
   const int tilesN = a.N / BN;
   const int tilesM = (a.M + BM - 1) / BM;
@@ -111,15 +112,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
   for (int i = 0; i < ACH; ++i) ra[i] = *(const uint4*)aptr[i];
 #pragma unroll
   for (int i = 0; i < BCH; ++i) rb[i] = *(const uint4*)bptr[i];
-#pragma unroll
-  for (int i = 0; i < ACH; ++i) sA[0][aoff[i]] = ra[i];
-#pragma unroll
-  for (int i = 0; i < BCH; ++i) sB[0][boff[i]] = rb[i];
-  __syncthreads();
 
   const int nk = a.K / BK;
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
+#pragma unroll
+    for (int i = 0; i < ACH; ++i) sA[aoff[i]] = ra[i];
+#pragma unroll
+    for (int i = 0; i < BCH; ++i) sB[boff[i]] = rb[i];
+    __syncthreads();
     if (kt + 1 < nk) {
 #pragma unroll
       for (int i = 0; i < ACH; ++i) ra[i] = *(const uint4*)(aptr[i] + (int64_t)(kt + 1) * BK);
@@ -133,23 +133,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
         const int row = wr * 32 * WM + i * 32 + l32;
-        fa[i] = sA[cur][row * 8 + (ch ^ (row & 7))];
+        fa[i] = sA[row * 8 + (ch ^ (row & 7))];
       }
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         const int row = wc * 32 * WN + j * 32 + l32;
-        fb[j] = sB[cur][row * 8 + (ch ^ (row & 7))];
+        fb[j] = sB[row * 8 + (ch ^ (row & 7))];
       }
 #pragma unroll
       for (int i = 0; i < WM; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j) Mma<T>::run(fa[i], fb[j], acc[i][j]);
-    }
-    if (kt + 1 < nk) {
-#pragma unroll
-      for (int i = 0; i < ACH; ++i) sA[cur ^ 1][aoff[i]] = ra[i];
-#pragma unroll
-      for (int i = 0; i < BCH; ++i) sB[cur ^ 1][boff[i]] = rb[i];
     }
     __syncthreads();
   }
@@ -184,16 +178,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     }
 }
 
-template <typename T, int EPI>
-static hipError_t launch(const GemmArgs& a, hipStream_t s) {
-  constexpr int WM = 2, WN = 2, BM = 64 * WM, BN = 64 * WN;
-  constexpr int BK = 128 / sizeof(T);
-  if (a.M <= 0) return hipSuccess;
-  if (a.N % BN != 0 || a.K % BK != 0 || a.K <= 0) return hipErrorInvalidValue;
-  if (EPI == EPI_QKV && ((a.heads * a.hd) % BN != 0 || !a.bias)) return hipErrorInvalidValue;
+template <typename T, int EPI, int WM, int WN>
+static hipError_t launch_tile(const GemmArgs& a, hipStream_t s) {
+  constexpr int BM = 64 * WM, BN = 64 * WN;
   const int nb = ((a.M + BM - 1) / BM) * (a.N / BN);
   hipLaunchKernelGGL((gemm_kernel<T, WM, WN, EPI>), dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int EPI>
+static hipError_t launch(const GemmArgs& a, hipStream_t s) {
+  constexpr int BK = 128 / sizeof(T);
+  if (a.M <= 0) return hipSuccess;
+  if (a.N % 128 != 0 || a.K % BK != 0 || a.K <= 0) return hipErrorInvalidValue;
+  if (EPI == EPI_QKV && ((a.heads * a.hd) % 128 != 0 || !a.bias)) return hipErrorInvalidValue;
+  // 256 x 128 tiles (waves of 128 x 64: fewer LDS bytes per MFMA) once there are enough of them
+  if (sizeof(T) == 2 && (int64_t)((a.M + 255) / 256) * (a.N / 128) >= 512) return launch_tile<T, EPI, 4, 2>(a, s);
+  return launch_tile<T, EPI, 2, 2>(a, s);
 }
 
 template <typename T>

@@ -25,7 +25,8 @@ hipError_t gemm(Dtype dt, Epi epi, const GemmArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- attention over segments
 struct AttnSeg { int32_t base, nf, n, npad; };   // tokens [base, base+nf*npad); frame stride npad, n valid
-struct AttnWork { int32_t seg, q0; };             // a 128-query tile of a segment
+struct AttnWork { int32_t seg, q0; };             // a query tile of a segment (attention_q_tile queries)
+int attention_q_tile(Dtype dt, int hd);
 hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void* vt, void* o,
                      int64_t mpad, int heads, int dim, const AttnSeg* segs, const AttnWork* work,
                      int nwork, hipStream_t s);

@@ -30,7 +30,8 @@ mf_status mf_op_attention(int32_t precision, int32_t head_dim, int32_t heads, in
     const int64_t end = (int64_t)s.base + (int64_t)s.nf * s.npad;
     if (end + 256 > mpad) return MF_EINVAL;
     const int qend = s.nf == 1 ? s.n : s.nf * s.npad;
-    for (int q0 = 0; q0 < qend; q0 += 128) wk.push_back({i, q0});
+    const int qt = attention_q_tile(precision == MF_BF16 ? DT_BF16 : DT_F32, head_dim);
+    for (int q0 = 0; q0 < qend; q0 += qt) wk.push_back({i, q0});
   }
   hipStream_t st = (hipStream_t)stream;
   void* dev = nullptr;
