@@ -46,7 +46,7 @@ def path_flops(wl) -> float:
     return tot
 
 
-def run_gpu(wl, precision: str, steps: int, warmup: int, sigma: float):
+def run_gpu(wl, precision: str, steps: int, warmup: int, sigma: float, profile: bool = True, graphs: bool = True):
     import torch
     import paper_2601_07154_amd as mfp
     blob = mf_synth.make_weights(wl.model, wl.seed_weights)
@@ -54,7 +54,8 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, sigma: float):
     rows = mfp.rows_per_frame(wl.height, wl.width)
     sched_frames = sum(w["size"] for w in __import__("oracle").motion.window_schedule(wl.frames, wl.window,
                                                                                         wl.overlap))
-    eng = mfp.Engine.from_model(wl.model, blob, precision=precision, max_tokens=sched_frames * rows + 64)
+    eng = mfp.Engine.from_model(wl.model, blob, precision=precision, max_tokens=sched_frames * rows + 64,
+                                graphs=graphs)
     K = (wl.fx, wl.fy, wl.cx, wl.cy)
     maps = torch.empty((wl.frames, wl.height, wl.width), device="cuda", dtype=torch.float32)
     sids = [eng.open_stream(wl.height, wl.width, wl.window, wl.overlap, K, sigma=sigma, ring_frames=wl.frames,
@@ -76,7 +77,8 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, sigma: float):
     for i in range(warmup):
         step(sids[i])
     recs_all.clear()
-    eng.profile(1)
+    if profile:
+        eng.profile(1)   # HIP events around every GEMM and attention launch (eager launches)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     n = 0
@@ -120,13 +122,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sigma", type=float, default=1000.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 256 MiB device copy (an elementwise torch kernel) so that HBM counters "
+                         "of the same profiler run can be scaled by a transfer of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
     wl = mf_synth.SMALL
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, device="cuda", dtype=torch.float32)   # 256 MiB
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)                                      # one kernel: reads and writes 256 MiB
+        torch.cuda.synchronize()
     r = run_gpu(wl, args.precision, args.steps, args.warmup, args.sigma)
     fps = r["frames"] / r["seconds"]
+    rg = run_gpu(wl, args.precision, args.steps, args.warmup, args.sigma, profile=False, graphs=True)
     ms_step = r["seconds"] * 1e3 / args.steps
     res = {
         "metric": "frames/sec pose+focus (BF16/FP8 vs FP32 at stated pose error); p50/p99 latency",
@@ -139,6 +151,7 @@ def main():
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(r["lat"], 50)), "p99": float(np.percentile(r["lat"], 99))},
         "path_tflops": path_flops(wl) * args.steps / r["seconds"] / 1e12,
+        "value_graphs_unprofiled": rg["frames"] / rg["seconds"],
     }
     prof = r["prof"]
     calls = max(1, prof["attn_global_calls"])

@@ -69,6 +69,8 @@ typedef struct mf_runtime_cfg {
   int64_t max_tokens_per_batch; /* token rows of one fused batch (0: 262144) */
   uint64_t hbm_budget_bytes;    /* device memory the engine may use (0: 80% of free memory) */
   void* stream;                 /* hipStream_t to run on, or NULL for an engine-owned stream */
+  int32_t use_graphs;           /* 1: each batch shape is captured once as a hipGraph and replayed */
+  int32_t reserved;
 } mf_runtime_cfg;
 
 typedef struct mf_stream_cfg {

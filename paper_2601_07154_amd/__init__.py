@@ -51,12 +51,13 @@ class Engine:
 
     def __init__(self, depth: int, dim: int, heads: int, mlp: int, weights: np.ndarray,
                  precision: str = "bf16", threaded: bool = False, max_tokens: int = 0,
-                 hbm_budget: int = 0, device: int = 0, stream: int | None = None, lib=None):
+                 hbm_budget: int = 0, device: int = 0, stream: int | None = None, graphs: bool = True,
+                 lib=None):
         self.lib = lib or _lib.lib()
         w = np.ascontiguousarray(weights, dtype=np.float32)
         m = _lib.ModelCfg(depth, dim, heads, mlp, 14, PRECISIONS[precision])
         rt = _lib.RuntimeCfg(device, 1 if threaded else 0, max_tokens, hbm_budget,
-                             C.c_void_p(stream) if stream else None)
+                             C.c_void_p(stream) if stream else None, 1 if graphs else 0, 0)
         h = C.c_void_p()
         _check(self.lib.mf_engine_create(C.byref(m), C.c_void_p(w.ctypes.data), w.size, C.byref(rt),
                                          C.byref(h)), "mf_engine_create", lib=self.lib)

@@ -26,7 +26,8 @@ class ModelCfg(C.Structure):
 
 class RuntimeCfg(C.Structure):
     _fields_ = [("device", C.c_int32), ("threaded", C.c_int32), ("max_tokens_per_batch", C.c_int64),
-                ("hbm_budget_bytes", C.c_uint64), ("stream", C.c_void_p)]
+                ("hbm_budget_bytes", C.c_uint64), ("stream", C.c_void_p), ("use_graphs", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class StreamCfg(C.Structure):

@@ -3,6 +3,7 @@
 // anchoring + focus and the focus maps.  Every arithmetic step runs in the kernels of this
 // library; the host only builds the batch tables.
 #include <hip/hip_runtime.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -63,6 +64,7 @@ class HipExecutor : public Executor {
     if (n != want) { err = "weight blob has " + std::to_string(n) + " floats, the model needs " + std::to_string(want); return MF_EINVAL; }
     HIPCHECK(hipSetDevice(rt.device));
     device_ = rt.device;
+    use_graphs_ = rt.use_graphs != 0;
     if (rt.stream) { st_ = (hipStream_t)rt.stream; own_stream_ = false; }
     else { HIPCHECK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking)); own_stream_ = true; }
     HIPCHECK(hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking));
@@ -242,25 +244,68 @@ class HipExecutor : public Executor {
       for (const BatchWindow& w : b.wins)
         if (w.poses) { put(po, w.poses, (size_t)w.size * 16 * sizeof(double)); po += (size_t)w.size * 16 * sizeof(double); }
     }
-    HIPCHECK(hipEventRecord(ev0_, st_));
-    HIPCHECK(hipMemcpyAsync(tab_dev_, tab_host_, off, hipMemcpyHostToDevice, st_));
     auto T = [&](size_t o) { return (void*)(tab_dev_ + o); };
-
-    // ---- the network over every frame window of the batch
-    if (!p.frames.empty()) {
-      rc = forward(p, (const FrameDesc*)T(o_frames), (const AttnSeg*)T(o_fsegs), (const AttnWork*)T(o_fwork),
-                   (const AttnSeg*)T(o_gsegs), (const AttnWork*)T(o_gwork), (const int32_t*)T(o_cam),
-                   depth_, err);
+    // Everything the batch runs on the device, in stream order.  The tables are read from the
+    // pinned buffer when the copy executes, so a captured graph replays with new contents.
+    auto enqueue = [&]() -> mf_status {
+      HIPCHECK(hipMemcpyAsync(tab_dev_, tab_host_, off, hipMemcpyHostToDevice, st_));
+      if (!p.frames.empty()) {
+        const mf_status r = forward(p, (const FrameDesc*)T(o_frames), (const AttnSeg*)T(o_fsegs),
+                                    (const AttnWork*)T(o_fwork), (const AttnSeg*)T(o_gsegs),
+                                    (const AttnWork*)T(o_gwork), (const int32_t*)T(o_cam), depth_, err);
+        if (r != MF_OK) return r;
+      }
+      if (pose_rows)
+        HIPCHECK(hipMemcpyAsync(tloc_ + (size_t)fwd_frames * 16, T(o_poses), (size_t)pose_rows * 16 * sizeof(double),
+                                hipMemcpyDeviceToDevice, st_));
+      HIPCHECK(chain_focus((const ChainGroup*)T(o_groups), (int)groups.size(), (const ChainWin*)T(o_cwins),
+                           (const StreamDev*)T(o_sdev), tloc_, pose9_, res_, st_));
+      HIPCHECK(focus_maps((const MapJob*)T(o_jobs), (int)jobs.size(), max_h, max_w, (const StreamDev*)T(o_sdev),
+                          res_, keys_, st_));
+      HIPCHECK(hipMemcpyAsync(res_host_, res_, (size_t)out_n * sizeof(mf_focus), hipMemcpyDeviceToHost, st_));
+      return MF_OK;
+    };
+    HIPCHECK(hipEventRecord(ev0_, st_));
+    // per-kernel timing brackets launches with events on the stream: profiled batches run eagerly
+    if (use_graphs_ && !profiling_) {
+      // every kernel argument and copy size follows from these counts (table offsets included)
+      char sig[256];
+      snprintf(sig, sizeof sig, "%lld/%d/%zu/%zu/%zu/%zu/%zu/%zu/%d/%d/%d/%d/%d/%zu/%d", (long long)p.mtot,
+               p.max_npad, p.frames.size(), p.fwork.size(), p.gwork.size(), groups.size(), cwins.size(), jobs.size(),
+               max_h, max_w, pose_rows, fwd_frames, out_n, off, profiling_ ? 1 : 0);
+      auto it = graphs_.find(sig);
+      if (it == graphs_.end()) {
+        if (graphs_.size() >= 64) clear_graphs();
+        GraphEntry ge;
+        // the per-kernel timing events of a profiled batch are recorded by the graph itself
+        prof_target_ = &ge.prof;
+        HIPCHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+        const mf_status r = enqueue();
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st_, &g);
+        prof_target_ = nullptr;
+        if (r != MF_OK) {
+          if (g) hipGraphDestroy(g);
+          return r;
+        }
+        if (ec != hipSuccess) {
+          err = std::string("hipStreamEndCapture failed: ") + hipGetErrorString(ec);
+          return MF_EDEVICE;
+        }
+        const hipError_t ei = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+          err = std::string("hipGraphInstantiate failed: ") + hipGetErrorString(ei);
+          return MF_EDEVICE;
+        }
+        it = graphs_.emplace(sig, std::move(ge)).first;
+      }
+      HIPCHECK(hipGraphLaunch(it->second.exec, st_));
+      replayed_prof_ = &it->second.prof;
+    } else {
+      rc = enqueue();
       if (rc != MF_OK) return rc;
     }
-    if (pose_rows)
-      HIPCHECK(hipMemcpyAsync(tloc_ + (size_t)fwd_frames * 16, T(o_poses), (size_t)pose_rows * 16 * sizeof(double),
-                              hipMemcpyDeviceToDevice, st_));
-    HIPCHECK(chain_focus((const ChainGroup*)T(o_groups), (int)groups.size(), (const ChainWin*)T(o_cwins),
-                         (const StreamDev*)T(o_sdev), tloc_, pose9_, res_, st_));
-    HIPCHECK(focus_maps((const MapJob*)T(o_jobs), (int)jobs.size(), max_h, max_w, (const StreamDev*)T(o_sdev),
-                        res_, keys_, st_));
-    HIPCHECK(hipMemcpyAsync(res_host_, res_, (size_t)out_n * sizeof(mf_focus), hipMemcpyDeviceToHost, st_));
     HIPCHECK(hipEventRecord(ev1_, st_));
     HIPCHECK(hipStreamSynchronize(st_));
     float ms = 0.0f;
@@ -437,8 +482,20 @@ class HipExecutor : public Executor {
     return MF_OK;
   }
 
+  void clear_graphs() {
+    for (auto& kv : graphs_) {
+      hipGraphExecDestroy(kv.second.exec);
+      for (auto& e : kv.second.prof) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+      }
+    }
+    graphs_.clear();
+  }
+
   mf_status ensure_tables(size_t bytes, std::string& err) {
     if (bytes <= tab_cap_) return MF_OK;
+    clear_graphs();   // captured copies point at the old table buffers
     if (tab_dev_) HIPCHECK(hipFree(tab_dev_));
     if (tab_host_) HIPCHECK(hipHostFree(tab_host_));
     tab_cap_ = align_up(bytes * 2, 1 << 20);
@@ -556,6 +613,15 @@ class HipExecutor : public Executor {
   size_t prof_used_ = 0;
   void prof_begin() {
     if (!profiling_) return;
+    if (prof_target_) {   // capturing: the graph owns its events
+      ProfEv e;
+      hipEventCreate(&e.a);
+      hipEventCreate(&e.b);
+      e.kind = 0;
+      prof_target_->push_back(e);
+      hipEventRecord(e.a, st_);
+      return;
+    }
     if (prof_used_ == prof_pool_.size()) {
       ProfEv e;
       hipEventCreate(&e.a);
@@ -566,24 +632,34 @@ class HipExecutor : public Executor {
   }
   void prof_end(int kind) {
     if (!profiling_) return;
+    if (prof_target_) {
+      prof_target_->back().kind = kind;
+      hipEventRecord(prof_target_->back().b, st_);
+      return;
+    }
     hipEventRecord(prof_pool_[prof_used_].b, st_);
     prof_pool_[prof_used_].kind = kind;
     prof_used_++;
   }
+  void account(const ProfEv& e) {
+    float ms = 0.0f;
+    hipEventSynchronize(e.b);
+    hipEventElapsedTime(&ms, e.a, e.b);
+    if (e.kind == 1) { prof_ag_ms_ += ms; prof_ag_calls_++; }
+    else if (e.kind == 2) prof_af_ms_ += ms;
+    else prof_gemm_ms_ += ms;
+  }
   void collect_profile(std::string&) {
-    for (size_t i = 0; i < prof_used_; ++i) {
-      float ms = 0.0f;
-      hipEventSynchronize(prof_pool_[i].b);
-      hipEventElapsedTime(&ms, prof_pool_[i].a, prof_pool_[i].b);
-      if (prof_pool_[i].kind == 1) { prof_ag_ms_ += ms; prof_ag_calls_++; }
-      else if (prof_pool_[i].kind == 2) prof_af_ms_ += ms;
-      else prof_gemm_ms_ += ms;
-    }
+    for (size_t i = 0; i < prof_used_; ++i) account(prof_pool_[i]);
     prof_used_ = 0;
+    if (replayed_prof_ && profiling_)
+      for (const ProfEv& e : *replayed_prof_) account(e);
+    replayed_prof_ = nullptr;
   }
 
   void release() {
     hipSetDevice(device_);
+    clear_graphs();
     auto F = [](void* p) { if (p) hipFree(p); };
     F(wdev_); F(Wp_); F(H1t_);
     for (auto& L : layers_) { F(L.Wqkv); F(L.Wo); F(L.W1); F(L.W2); }
@@ -628,6 +704,14 @@ class HipExecutor : public Executor {
   std::map<std::pair<int, int>, int> pe_index_;
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   bool profiling_ = false;
+  bool use_graphs_ = false;
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    std::vector<ProfEv> prof;   // timing events recorded inside the graph (profiled shapes)
+  };
+  std::map<std::string, GraphEntry> graphs_;
+  std::vector<ProfEv>* prof_target_ = nullptr;
+  const std::vector<ProfEv>* replayed_prof_ = nullptr;
   double prof_ag_ms_ = 0, prof_af_ms_ = 0, prof_gemm_ms_ = 0;
   int64_t prof_ag_calls_ = 0;
 };

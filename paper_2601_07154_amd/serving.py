@@ -1,0 +1,110 @@
+"""Request loop for serving many video streams on one engine (continuous batching).
+
+Streams arrive over time (arrival second, length, H, W); each is admitted when the engine's HBM
+budget allows (mf_open_stream returns MF_EAGAIN until memory frees up), its frames are pushed at
+their capture rate (or all at once in the throughput regime), and results are polled as the
+engine's scheduler thread completes windows.  Every window that is ready when a batch starts
+joins that batch, whatever stream it belongs to.
+
+Reported per frame: latency = t_ready - t_push, split into buffering (waiting for the window's
+last frame), queueing and compute is left to the caller from the records' timestamps.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import MF_EAGAIN, MF_ECLOSED, MF_OK
+
+
+@dataclass
+class StreamSpec:
+    arrival: float      # seconds after the start
+    length: int         # frames
+    height: int
+    width: int
+    seed: int = 0
+
+
+@dataclass
+class StreamState:
+    spec: StreamSpec
+    sid: int = -1
+    pushed: int = 0
+    done: bool = False
+    admitted_at: float = -1.0
+    records: list = field(default_factory=list)
+
+
+def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float = 30.0,
+          paced: bool = True, poll_cap: int = 256, time_limit: float = 600.0, sigma: float = 1000.0,
+          emit_maps: bool = False, push_chunk: int = 1):
+    """Run the streams to completion on a threaded engine.
+
+    frame_pool(height, width) -> array/tensor [P, 3, H, W] of frames pushed cyclically.
+    K_of(height, width) -> intrinsics.  Returns dict(records per stream, wall seconds, stats).
+    """
+    states = [StreamState(s) for s in specs]
+    pending = list(range(len(states)))          # not yet admitted, in arrival order
+    active = []
+    t0 = time.perf_counter()
+    pools = {}
+    while True:
+        now = time.perf_counter() - t0
+        if now > time_limit:
+            raise TimeoutError("serving run exceeded its time limit")
+        # admission in arrival order
+        while pending and states[pending[0]].spec.arrival <= now:
+            st = states[pending[0]]
+            s = st.spec
+            sid = engine.open_stream(s.height, s.width, window, overlap, K_of(s.height, s.width), sigma=sigma,
+                                     emit_maps=emit_maps, ring_frames=2 * window + 8 * push_chunk,
+                                     allow_again=True)
+            if sid < 0:
+                break                            # budget held by other streams: retry later
+            st.sid = sid
+            st.admitted_at = now
+            active.append(st)
+            pending.pop(0)
+        # pushes: frames whose capture time has come (paced) or everything (throughput regime)
+        for st in active:
+            s = st.spec
+            if st.pushed >= s.length:
+                continue
+            due = s.length if not paced else min(s.length, int((now - st.admitted_at) * fps) + 1)
+            key = (s.height, s.width)
+            if key not in pools:
+                pools[key] = frame_pool(s.height, s.width)
+            pool = pools[key]
+            while st.pushed < due:
+                n = min(push_chunk, due - st.pushed, pool.shape[0] - st.pushed % pool.shape[0])
+                off = st.pushed % pool.shape[0]
+                rc = engine.push_frames(st.sid, pool[off:off + n], eos=st.pushed + n == s.length, allow_again=True)
+                if rc == MF_EAGAIN:
+                    break
+                st.pushed += n
+        # polls
+        for st in list(active):
+            r, rc = engine.poll(st.sid, poll_cap)
+            if len(r):
+                st.records.append(r)
+            if rc == MF_ECLOSED:
+                st.done = True
+                active.remove(st)
+        if not pending and not active:
+            break
+        if not paced:
+            time.sleep(0.0005)
+        else:
+            time.sleep(0.001)
+    wall = time.perf_counter() - t0
+    recs = [np.concatenate(st.records) if st.records else np.zeros(0) for st in states]
+    return dict(records=recs, wall=wall, stats=engine.stats(), states=states)
+
+
+def latency_summary(recs_list):
+    lat = np.concatenate([(r["t_ready"] - r["t_push"]) for r in recs_list if len(r)]) * 1e3
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "frames": int(lat.size)}

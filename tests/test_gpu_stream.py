@@ -135,3 +135,39 @@ def test_tiny_stream_end_to_end(prec):
         np.testing.assert_array_equal(recs["valid"] & 1, ref["track"]["valid"].astype(np.int32))
     else:
         assert err_T < 0.05
+
+
+def test_graph_replays_match_eager():
+    """A batch shape is captured once as a hipGraph and replayed: every replay (with unrelated eager
+    work and synchronisation in between) equals the eager launch sequence bit for bit."""
+    torch = torch_cuda()
+    m = mf()
+    model = mf_synth.ModelConfig(4, 384, 6, 1536)
+    blob = mf_synth.make_weights(model, 3)
+    H, W, L, O, N = 112, 168, 8, 4, 20
+    K = (120.0, 120.0, W / 2, H / 2)
+    frames = torch.from_numpy(mf_synth.make_frames(N, H, W, 9)).cuda()
+
+    def run(eng):
+        sid = eng.open_stream(H, W, L, O, K, sigma=300.0, ring_frames=N, result_frames=N)
+        eng.push_frames(sid, frames, eos=True)
+        eng.sync()
+        mp = np.zeros((N, H, W), np.float32)
+        r, _ = eng.poll(sid, N, mp)
+        eng.poll(sid, 1)
+        return r, mp
+
+    eager = m.Engine.from_model(model, blob, precision="bf16", max_tokens=8192, graphs=False)
+    ref, ref_maps = run(eager)
+    eager.close()
+    eng = m.Engine.from_model(model, blob, precision="bf16", max_tokens=8192, graphs=True)
+    x = torch.randn(64, 384, device="cuda")
+    for rep in range(4):
+        got, maps = run(eng)
+        for f in ("T_w2c", "pose9", "a_world", "u", "v", "valid", "peak_x", "peak_y", "frame", "window"):
+            np.testing.assert_array_equal(got[f], ref[f], err_msg=f"replay {rep} field {f}")
+        np.testing.assert_array_equal(maps, ref_maps)
+        y = torch.empty(64, 384, device="cuda")           # eager work between replays
+        m.op_layernorm("fp32", x, y, torch.ones(384, device="cuda"), torch.zeros(384, device="cuda"))
+        torch.cuda.synchronize()
+    eng.close()

@@ -267,3 +267,20 @@ def test_threaded_engine_under_thread_sanitizer(tmp_path):
     assert "ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
     assert r.returncode == 0, r.stdout + r.stderr[-2000:]
     assert "bad=0" in r.stdout
+
+
+def test_serving_loop_on_host_stub(hostlib):
+    """The request loop admits streams as the budget frees up and returns every frame in order."""
+    from paper_2601_07154_amd import serving
+    per = 3 * 28 * 28 * 4 * (2 * 8 + 8) + 512 * 168
+    eng = engine(hostlib, threaded=True, hbm_budget=(1 << 20) + 3 * per + 1000)   # 3 streams at a time
+    rng = np.random.default_rng(0)
+    specs = [serving.StreamSpec(0.0, int(rng.integers(5, 60)), 28, 28) for i in range(10)]   # all at once
+    out = serving.serve(eng, specs, lambda H, W: np.zeros((16, 3, H, W), np.float32), 8, 4,
+                        lambda H, W: (50.0, 50.0, W / 2, H / 2), paced=False, time_limit=60)
+    for s, r in zip(specs, out["records"]):
+        assert list(r["frame"]) == list(range(s.length))
+    lat = serving.latency_summary(out["records"])
+    assert lat["frames"] == sum(s.length for s in specs)
+    assert out["stats"]["streams_pending"] > 0          # admission had to wait
+    eng.close()
