@@ -18,6 +18,32 @@
 
 namespace mf {
 
+
+// Validity bits of the 16 keys a lane holds in a 32-key sub-tile starting at key kb0 + 4g:
+// keys kb0 + 4g + 8j + i (j, i < 4) -> bit 4j + i.  A key is valid if it lies in the segment and
+// not in the padding rows of its frame (frames every npad >= 8 rows, n valid).  One modulo per
+// sub-tile; the rest walks the frame offset incrementally (no per-key division).
+MF_DEV unsigned key_mask(int kb0, int g, int key_end, int npad, int n) {
+  const int k0 = kb0 + 4 * g;
+  int rel = k0 % npad;
+  unsigned bits = 0u;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j) {
+      rel += 8;
+      rel = rel >= npad ? rel - npad : rel;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int ri = rel + i;
+      ri = ri >= npad ? ri - npad : ri;
+      const bool ok = (k0 + 8 * j + i < key_end) & (ri < n);
+      bits |= (ok ? 1u : 0u) << (4 * j + i);
+    }
+  }
+  return bits;
+}
+
 template <typename T, int HD>
 struct AttnCfg {
   static constexpr int BK = 64;                          // keys per tile
@@ -31,12 +57,12 @@ struct AttnCfg {
 
 // S^T (32 keys x 32 queries) += K_frag x Q^T_frag over the head dimension.
 template <typename T, int HD>
-MF_DEV void qk_tile(const uint4* sK, int key_row, const uint4* qf, int g, f32x16& s) {
+MF_DEV void qk_tile(const u32x4* sK, int key_row, const u32x4* qf, int g, f32x16& s) {
   using C = AttnCfg<T, HD>;
 #pragma unroll
   for (int f = 0; f < C::QF; ++f) {
     const int ch = 2 * f + g;
-    const uint4 kf = sK[key_row * C::KCPR + (ch ^ (key_row % C::KCPR))];
+    const u32x4 kf = sK[key_row * C::KCPR + (ch ^ (key_row % C::KCPR))];
     if constexpr (sizeof(T) == 2) {
       s = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf, *(const bf16x8*)&qf[f], s, 0, 0, 0);
     } else {
@@ -50,7 +76,7 @@ MF_DEV void qk_tile(const uint4* sK, int key_row, const uint4* qf, int g, f32x16
 
 // O^T (32 d x 32 queries) += V^T (rows d, keys of sub-tile kb) x P^T (from the score registers).
 template <typename T, int HD>
-MF_DEV void pv_tile(const uint4* sV, int d_row, int kb, int g, const f32x16& p, f32x16& o) {
+MF_DEV void pv_tile(const u32x4* sV, int d_row, int kb, int g, const f32x16& p, f32x16& o) {
   using C = AttnCfg<T, HD>;
   const int sw = d_row % C::VCPR;
   if constexpr (sizeof(T) == 2) {
@@ -58,10 +84,10 @@ MF_DEV void pv_tile(const uint4* sV, int d_row, int kb, int g, const f32x16& p, 
     for (int j2 = 0; j2 < 2; ++j2) {
       // keys kb*32 + 16*j2 + {4g..4g+3} (chunk c0, half g) and + 8 (chunk c0+1, half g)
       const int c0 = 4 * kb + 2 * j2;
-      const uint2* row = (const uint2*)(sV + d_row * C::VCPR);
-      const uint2 lo = row[2 * (c0 ^ sw) + g];
-      const uint2 hi = row[2 * ((c0 + 1) ^ sw) + g];
-      uint4 vf = {lo.x, lo.y, hi.x, hi.y};
+      const u32x2* row = (const u32x2*)(sV + d_row * C::VCPR);
+      const u32x2 lo = row[2 * (c0 ^ sw) + g];
+      const u32x2 hi = row[2 * ((c0 + 1) ^ sw) + g];
+      u32x4 vf = {lo.x, lo.y, hi.x, hi.y};
       bf16x8 pf;
 #pragma unroll
       for (int r = 0; r < 8; ++r) pf[r] = (bf16)p[8 * j2 + r];
@@ -71,7 +97,7 @@ MF_DEV void pv_tile(const uint4* sV, int d_row, int kb, int g, const f32x16& p, 
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       // keys kb*32 + 8*jj + 4g + {0..3}: chunk 8kb + 2jj + g
-      const uint4 vf = sV[d_row * C::VCPR + ((8 * kb + 2 * jj + g) ^ sw)];
+      const u32x4 vf = sV[d_row * C::VCPR + ((8 * kb + 2 * jj + g) ^ sw)];
       o = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(vf.x), p[4 * jj + 0], o, 0, 0, 0);
       o = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(vf.y), p[4 * jj + 1], o, 0, 0, 0);
       o = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(vf.z), p[4 * jj + 2], o, 0, 0, 0);
@@ -89,8 +115,8 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
                                                    float scale_log2) {
   using C = AttnCfg<T, HD>;
   constexpr int BK = C::BK;
-  __shared__ uint4 sK[2][C::KCH];
-  __shared__ uint4 sV[2][C::VCH];
+  __shared__ u32x4 sK[2][C::KCH];
+  __shared__ u32x4 sV[2][C::VCH];
 
   const int nb = nwork * heads;
   const int bid = xcd_remap(blockIdx.x, nb);
@@ -107,9 +133,9 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
   const T* Vh = Vt + (int64_t)h * HD * mpad + sg.base;
 
   // Q^T fragments (B operand): lane (query l32, group g) holds chunks 2f+g of its query row.
-  uint4 qf[C::QF];
+  u32x4 qf[C::QF];
   {
-    const uint4* qr = (const uint4*)(Qh + (int64_t)qrow * HD);
+    const u32x4* qr = (const u32x4*)(Qh + (int64_t)qrow * HD);
 #pragma unroll
     for (int f = 0; f < C::QF; ++f) qf[f] = qr[2 * f + g];
   }
@@ -117,17 +143,17 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
   // Tile loaders: chunk c of the K tile is (row c / KCPR, col c % KCPR); of the V^T tile
   // (d row c / VCPR, key chunk c % VCPR).
   constexpr int KPT = C::KCH / 256, VPT = C::VCH / 256;
-  uint4 rk[KPT], rv[VPT];
+  u32x4 rk[KPT], rv[VPT];
   auto load_tile = [&](int kt) {
 #pragma unroll
     for (int i = 0; i < KPT; ++i) {
       const int c = tid + i * 256, row = c / C::KCPR, col = c % C::KCPR;
-      rk[i] = *(const uint4*)(Kh + (int64_t)(kt + row) * HD + col * (16 / sizeof(T)));
+      rk[i] = *(const u32x4*)(Kh + (int64_t)(kt + row) * HD + col * (16 / sizeof(T)));
     }
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int c = tid + i * 256, row = c / C::VCPR, col = c % C::VCPR;
-      rv[i] = *(const uint4*)(Vh + (int64_t)row * mpad + kt + col * (16 / sizeof(T)));
+      rv[i] = *(const u32x4*)(Vh + (int64_t)row * mpad + kt + col * (16 / sizeof(T)));
     }
   };
   auto store_tile = [&](int buf) {
@@ -158,7 +184,7 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
 
   for (int it = 0; it < ntiles; ++it) {
     const int cur = it & 1, kt = it * BK;
-    if (it + 1 < ntiles) load_tile(kt + BK);
+    load_tile(it + 1 < ntiles ? kt + BK : kt);   // unconditional: the registers stay plain values
 
     f32x16 s[2];
 #pragma unroll
@@ -172,13 +198,11 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
     const bool full = kt + BK <= (f0 * sg.npad + sg.n) && kt + BK <= key_end;
     if (!full) {   // branch-free select: no divergent control flow around the scores
 #pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
+      for (int kb = 0; kb < 2; ++kb) {
+        const unsigned bits = key_mask(kt + kb * 32, g, key_end, sg.npad, sg.n);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const unsigned key = (unsigned)(kt + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3));
-          const bool ok = (key < (unsigned)key_end) & ((key % (unsigned)sg.npad) < (unsigned)sg.n);
-          s[kb][r] = ok ? s[kb][r] : -INFINITY;
-        }
+        for (int r = 0; r < 16; ++r) s[kb][r] = ((bits >> r) & 1u) ? s[kb][r] : -INFINITY;
+      }
     }
     float mx = -INFINITY;
 #pragma unroll
@@ -260,8 +284,8 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
                                                          const AttnSeg* __restrict__ segs,
                                                          const AttnWork* __restrict__ work, int nwork,
                                                          float c) {
-  __shared__ uint4 sK[2][BK * CPR];
-  __shared__ uint4 sV[2][HD * CPR];
+  __shared__ u32x4 sK[2][BK * CPR];
+  __shared__ u32x4 sV[2][HD * CPR];
   const int nb = nwork * heads;
   const int bid = xcd_remap(blockIdx.x, nb);
   const int h = bid % heads, wi = bid / heads;
@@ -276,21 +300,21 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
   const bf16* Kh = K + ((int64_t)h * mpad + sg.base) * HD;
   const bf16* Vh = Vt + (int64_t)h * HD * mpad + sg.base;
 
-  uint4 qf[2][4];
+  u32x4 qf[2][4];
 #pragma unroll
   for (int hb = 0; hb < 2; ++hb) {
-    const uint4* qr = (const uint4*)(Qh + (int64_t)(qbase + hb * 32 + l32) * HD);
+    const u32x4* qr = (const u32x4*)(Qh + (int64_t)(qbase + hb * 32 + l32) * HD);
 #pragma unroll
     for (int f = 0; f < 4; ++f) qf[hb][f] = qr[2 * f + g];
   }
 
-  uint4 rk[2], rv[2];
+  u32x4 rk[2], rv[2];
   auto load_tile = [&](int kt) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int ch = tid + i * 256, row = ch >> 3, col = ch & 7;
-      rk[i] = *(const uint4*)(Kh + (int64_t)(kt + row) * HD + col * 8);
-      rv[i] = *(const uint4*)(Vh + (int64_t)row * mpad + kt + col * 8);
+      rk[i] = *(const u32x4*)(Kh + (int64_t)(kt + row) * HD + col * 8);
+      rv[i] = *(const u32x4*)(Vh + (int64_t)row * mpad + kt + col * 8);
     }
   };
   auto store_tile = [&](int buf) {
@@ -320,103 +344,97 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
 
   for (int it = 0; it < ntiles; ++it) {
     const int cur = it & 1, kt = it * BK;
-    if (it + 1 < ntiles) load_tile(kt + BK);
+    load_tile(it + 1 < ntiles ? kt + BK : kt);   // unconditional: the registers stay plain values
 
-    // S^T for 64 keys x (2 x 32) queries; K fragments shared by both query blocks
-    f32x16 s[2][2];
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
-      const int krow = kb * 32 + l32;
-      uint4 kf[4];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) kf[f] = sK[cur][krow * CPR + ((2 * f + g) ^ (krow & 7))];
-#pragma unroll
-      for (int hb = 0; hb < 2; ++hb) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) s[hb][kb][r] = 0.0f;
-#pragma unroll
-        for (int f = 0; f < 4; ++f)
-          s[hb][kb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf[f], *(const bf16x8*)&qf[hb][f],
-                                                               s[hb][kb], 0, 0, 0);
-      }
-    }
     const int f0 = kt / sg.npad;
     const bool full = kt + BK <= (f0 * sg.npad + sg.n) && kt + BK <= key_end;
-    if (!full) {   // branch-free select: no divergent control flow around the scores
+    // two 32-key steps per tile: S^T, online softmax and PV per step keep the live registers low
 #pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
+    for (int kb = 0; kb < 2; ++kb) {
+      f32x16 s[2];
+      {
+        const int krow = kb * 32 + l32;
+        u32x4 kf[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) kf[f] = sK[cur][krow * CPR + ((2 * f + g) ^ (krow & 7))];
+#pragma unroll
+        for (int hb = 0; hb < 2; ++hb) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) s[hb][r] = 0.0f;
+#pragma unroll
+          for (int f = 0; f < 4; ++f)
+            s[hb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf[f], *(const bf16x8*)&qf[hb][f],
+                                                            s[hb], 0, 0, 0);
+        }
+      }
+      if (!full) {   // branch-free select: no divergent control flow around the scores
+        const unsigned bits = key_mask(kt + kb * 32, g, key_end, sg.npad, sg.n);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const unsigned key = (unsigned)(kt + kb * 32 + 8 * (r >> 2) + 4 * g + (r & 3));
-          const bool ok = (key < (unsigned)key_end) & ((key % (unsigned)sg.npad) < (unsigned)sg.n);
-          s[0][kb][r] = ok ? s[0][kb][r] : -INFINITY;
-          s[1][kb][r] = ok ? s[1][kb][r] : -INFINITY;
+          const bool ok = (bits >> r) & 1u;
+          s[0][r] = ok ? s[0][r] : -INFINITY;
+          s[1][r] = ok ? s[1][r] : -INFINITY;
         }
-    }
-    // running max: moved only when a tile max exceeds it by more than 8 (log2 units)
-    float mx[2];
-#pragma unroll
-    for (int hb = 0; hb < 2; ++hb) {
-      float a = s[hb][0][0];
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) a = fmaxf(a, s[hb][kb][r]);
-      a = fmaxf(a, __shfl_xor(a, 32, 64));
-      mx[hb] = a * c;
-    }
-    const bool grow = (mx[0] > m_run[0] + 8.0f) || (mx[1] > m_run[1] + 8.0f);
-    if (__any(grow)) {
+      }
+      // running max: moved only when a step's max exceeds it by more than 8 (log2 units)
+      float mx[2];
 #pragma unroll
       for (int hb = 0; hb < 2; ++hb) {
-        const float m_new = fmaxf(m_run[hb], mx[hb]);
-        const float alpha = m_new == -INFINITY ? 1.0f : fast_exp2(m_run[hb] - m_new);
-        m_run[hb] = m_new;
-        l_run[hb] *= alpha;
+        float a = s[hb][0];
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) o[hb][t][r] *= alpha;
+        for (int r = 1; r < 16; ++r) a = fmaxf(a, s[hb][r]);
+        a = fmaxf(a, __shfl_xor(a, 32, 64));
+        mx[hb] = a * c;
       }
-    }
-    // probabilities (bf16, B operand of PV) and their row sums
-    bf16x8 pf[2][2][2];
+      const bool grow = (mx[0] > m_run[0] + 8.0f) || (mx[1] > m_run[1] + 8.0f);
+      if (__any(grow)) {
 #pragma unroll
-    for (int hb = 0; hb < 2; ++hb) {
-      const float nm = -m_run[hb];
-      float ls = 0.0f;
+        for (int hb = 0; hb < 2; ++hb) {
+          const float m_new = fmaxf(m_run[hb], mx[hb]);
+          const float alpha = m_new == -INFINITY ? 1.0f : fast_exp2(m_run[hb] - m_new);
+          m_run[hb] = m_new;
+          l_run[hb] *= alpha;
 #pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
+          for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) o[hb][t][r] *= alpha;
+        }
+      }
+      // probabilities (bf16, B operand of PV) and their row sums
+      bf16x8 pf[2][2];
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb) {
+        const float nm = -m_run[hb];
+        float ls = 0.0f;
 #pragma unroll
         for (int j2 = 0; j2 < 2; ++j2) {
 #pragma unroll
-          for (int r = 0; r < 8; ++r) pf[hb][kb][j2][r] = (bf16)fast_exp2(fmaf(s[hb][kb][8 * j2 + r], c, nm));
+          for (int r = 0; r < 8; ++r) pf[hb][j2][r] = (bf16)fast_exp2(fmaf(s[hb][8 * j2 + r], c, nm));
 #pragma unroll
           for (int r = 0; r < 8; r += 2) {
-            const bf16x2_t pr = {pf[hb][kb][j2][r], pf[hb][kb][j2][r + 1]};
+            const bf16x2_t pr = {pf[hb][j2][r], pf[hb][j2][r + 1]};
             ls = __builtin_amdgcn_fdot2_f32_bf16(pr, ones, ls, false);
           }
         }
-      l_run[hb] += ls;
-    }
-    // O^T += V^T P^T; V fragments shared by both query blocks
+        l_run[hb] += ls;
+      }
+      // O^T += V^T P^T for this step's 32 keys; V fragments shared by both query blocks
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int drow = t * 32 + l32;
-      const int sw = drow & 7;
-      const uint2* row = (const uint2*)(sV[cur] + drow * CPR);
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
+      for (int t = 0; t < 2; ++t) {
+        const int drow = t * 32 + l32;
+        const int sw = drow & 7;
+        const u32x2* row = (const u32x2*)(sV[cur] + drow * CPR);
 #pragma unroll
         for (int j2 = 0; j2 < 2; ++j2) {
           const int c0 = 4 * kb + 2 * j2;
-          const uint2 lo = row[2 * (c0 ^ sw) + g];
-          const uint2 hi = row[2 * ((c0 + 1) ^ sw) + g];
-          const uint4 vf = {lo.x, lo.y, hi.x, hi.y};
+          const u32x2 lo = row[2 * (c0 ^ sw) + g];
+          const u32x2 hi = row[2 * ((c0 + 1) ^ sw) + g];
+          const u32x4 vf = {lo.x, lo.y, hi.x, hi.y};
 #pragma unroll
           for (int hb = 0; hb < 2; ++hb)
-            o[hb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&vf, pf[hb][kb][j2], o[hb][t], 0, 0, 0);
+            o[hb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&vf, pf[hb][j2], o[hb][t], 0, 0, 0);
         }
+      }
     }
     if (it + 1 < ntiles) {
       __syncthreads();

@@ -8,6 +8,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Native vector types for 16- and 8-byte fragments.  (HIP's uint4/uint2 are structs with
+// unions; arrays of them kept across loop iterations were demoted to scratch memory.)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 #define MF_DEV __device__ __forceinline__
 

@@ -16,12 +16,12 @@ namespace mf {
 
 template <typename T> struct Mma;
 template <> struct Mma<bf16> {
-  static MF_DEV void run(const uint4& a, const uint4& b, f32x16& c) {
+  static MF_DEV void run(const u32x4& a, const u32x4& b, f32x16& c) {
     c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&a, *(const bf16x8*)&b, c, 0, 0, 0);
   }
 };
 template <> struct Mma<float> {
-  static MF_DEV void run(const uint4& a, const uint4& b, f32x16& c) {
+  static MF_DEV void run(const u32x4& a, const u32x4& b, f32x16& c) {
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
@@ -67,8 +67,8 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   constexpr int BK = 8 * EPC;           // elements per 128-byte row slice
   constexpr int ACH = BM * 8 / 256, BCH = BN * 8 / 256;   // chunks per thread
   // one LDS stage: the next k-slice is prefetched into registers while this one is consumed
-  __shared__ uint4 sA[BM * 8];
-  __shared__ uint4 sB[BN * 8];
+  __shared__ u32x4 sA[BM * 8];
+  __shared__ u32x4 sB[BN * 8];
 
   const int tilesN = a.N / BN;
   const int tilesM = (a.M + BM - 1) / BM;
@@ -107,11 +107,11 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  uint4 ra[ACH], rb[BCH];
+  u32x4 ra[ACH], rb[BCH];
 #pragma unroll
-  for (int i = 0; i < ACH; ++i) ra[i] = *(const uint4*)aptr[i];
+  for (int i = 0; i < ACH; ++i) ra[i] = *(const u32x4*)aptr[i];
 #pragma unroll
-  for (int i = 0; i < BCH; ++i) rb[i] = *(const uint4*)bptr[i];
+  for (int i = 0; i < BCH; ++i) rb[i] = *(const u32x4*)bptr[i];
 
   const int nk = a.K / BK;
   for (int kt = 0; kt < nk; ++kt) {
@@ -120,15 +120,16 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < BCH; ++i) sB[boff[i]] = rb[i];
     __syncthreads();
-    if (kt + 1 < nk) {
+    {   // prefetch the next k-slice (the last iteration re-reads its own: no conditional registers)
+      const int64_t kn = (int64_t)min(kt + 1, nk - 1) * BK;
 #pragma unroll
-      for (int i = 0; i < ACH; ++i) ra[i] = *(const uint4*)(aptr[i] + (int64_t)(kt + 1) * BK);
+      for (int i = 0; i < ACH; ++i) ra[i] = *(const u32x4*)(aptr[i] + kn);
 #pragma unroll
-      for (int i = 0; i < BCH; ++i) rb[i] = *(const uint4*)(bptr[i] + (int64_t)(kt + 1) * BK);
+      for (int i = 0; i < BCH; ++i) rb[i] = *(const u32x4*)(bptr[i] + kn);
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      uint4 fa[WM], fb[WN];
+      u32x4 fa[WM], fb[WN];
       const int ch = 2 * kk + g;
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
