@@ -6,8 +6,9 @@
 // between frames are masked.  softmax(Q K^T / sqrt(hd)) V is computed per head with the
 // running-max rescaling of flash attention: scores never leave registers.
 //
-// Each workgroup (4 waves) takes 128 queries of one segment and one head; each wave owns
-// 32 queries.  Scores are computed transposed, S^T = K Q^T, so that each lane holds one query
+// attn_kernel (fp32, and bf16 with hd 32): each workgroup (4 waves) takes 128 queries of one
+// segment and one head; each wave owns 32 queries.  attn_kernel_v2 (bf16, hd 64) doubles the
+// queries per wave (below).  Scores are computed transposed, S^T = K Q^T, so that each lane holds one query
 // column: the row max is a reduction over the lane's 16 values plus one exchange between
 // the two lane halves.  The probabilities feed O^T = V^T P^T directly from registers as the
 // B operand (their k order, {4g..4g+3, 8+4g..8+4g+3}, is matched by the V^T fragments read
@@ -266,17 +267,39 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
 
 // ------------------------------------------------------------------ bf16, hd = 64, 64 queries/wave
 // Each wave owns two 32-query blocks that share every K and V^T fragment read from LDS (half
-// the LDS traffic per flop of one block per wave); a workgroup covers 256 queries.  The running
-// max is only moved when some lane's tile max exceeds it by more than 2^8 (the probabilities
-// then stay <= 256, exact in fp32 and representable in bf16), so the O rescale and its
-// accumulator traffic are rare.  Row sums are taken from the bf16-rounded probabilities that
-// the PV product uses (v_dot2), so numerator and denominator see the same weights.
+// the LDS traffic per flop of one block per wave); a workgroup covers 256 queries.  Keys are
+// staged in LDS tiles of 128 (double-buffered, two barriers per tile) and consumed in 32-key
+// steps that are software-pipelined: the S^T MFMAs of step t+1 are issued before the softmax
+// of step t, so the matrix cores work while the vector ALUs exponentiate.  The running max is
+// only moved when a step's max exceeds it by more than 2^8 (the probabilities then stay <= 256,
+// exact in fp32 and representable in bf16), so the O rescale is rare.  Row sums are taken
+// from the bf16-rounded probabilities that the PV product uses (v_dot2), so numerator and
+// denominator see the same weights.  V^T tiles are stored with the keys of each 16-key group
+// reordered [0-3, 8-11, 4-7, 12-15] so that a lane's PV fragment is one 16-byte LDS read.
 namespace v2 {
-constexpr int HD = 64, BK = 64, QW = 64, QT = 256;
-constexpr int CPR = 8;   // 16-byte chunks per 128-byte row (K rows: 64 d; V^T rows: 64 keys)
+constexpr int HD = 64, KT = 128, KS = 32, QW = 64, QT = 256;
+constexpr int KCPR = 8;    // 16-byte chunks per K row (64 d)
+constexpr int VCPR = 16;   // 16-byte chunks per V^T row (128 keys)
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 MF_DEV float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// S^T (32 keys x 32 queries) for both query blocks of the wave, keys `krow0`.. of LDS K tile.
+MF_DEV void qk_step(const u32x4* sKb, int krow0, int l32, int g, const u32x4 (&qf)[2][4], f32x16 (&s)[2]) {
+  const int krow = krow0 + l32;
+  u32x4 kf[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) kf[f] = sKb[krow * KCPR + ((2 * f + g) ^ ((krow >> 1) & 7))];
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s[hb][r] = 0.0f;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      s[hb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf[f], *(const bf16x8*)&qf[hb][f], s[hb], 0, 0, 0);
+  }
+}
 
 __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict__ Q, const bf16* __restrict__ K,
                                                          const bf16* __restrict__ Vt, bf16* __restrict__ O,
@@ -284,8 +307,8 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
                                                          const AttnSeg* __restrict__ segs,
                                                          const AttnWork* __restrict__ work, int nwork,
                                                          float c) {
-  __shared__ u32x4 sK[2][BK * CPR];
-  __shared__ u32x4 sV[2][HD * CPR];
+  __shared__ u32x4 sK[2][KT * KCPR];
+  __shared__ u32x4 sV[2][HD * VCPR];
   const int nb = nwork * heads;
   const int bid = xcd_remap(blockIdx.x, nb);
   const int h = bid % heads, wi = bid / heads;
@@ -308,21 +331,33 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
     for (int f = 0; f < 4; ++f) qf[hb][f] = qr[2 * f + g];
   }
 
-  u32x4 rk[2], rv[2];
+  // K tile: thread -> chunks (row tid/8 + 32 i, col tid%8), i < 4.  V^T tile: thread -> row
+  // tid/4, keys 32 (tid%4) .. +31 (two 16-key groups), stored reordered (see above).
+  u32x4 rk[4], rv[4];
   auto load_tile = [&](int kt) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int ch = tid + i * 256, row = ch >> 3, col = ch & 7;
+    for (int i = 0; i < 4; ++i) {
+      const int row = (tid >> 3) + 32 * i, col = tid & 7;
       rk[i] = *(const u32x4*)(Kh + (int64_t)(kt + row) * HD + col * 8);
-      rv[i] = *(const u32x4*)(Vh + (int64_t)row * mpad + kt + col * 8);
     }
+    const u32x4* vsrc = (const u32x4*)(Vh + (int64_t)(tid >> 2) * mpad + kt + (tid & 3) * 32);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rv[i] = vsrc[i];
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int ch = tid + i * 256, row = ch >> 3, col = ch & 7;
-      sK[buf][row * CPR + (col ^ (row & 7))] = rk[i];
-      sV[buf][row * CPR + (col ^ (row & 7))] = rv[i];
+    for (int i = 0; i < 4; ++i) {
+      const int row = (tid >> 3) + 32 * i, col = tid & 7;
+      sK[buf][row * KCPR + (col ^ ((row >> 1) & 7))] = rk[i];
+    }
+    const int vrow = tid >> 2, sw = vrow & 15;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int ch = 4 * (tid & 3) + 2 * p;                         // first chunk of this 16-key group
+      const u32x4 lo = {rv[2 * p].x, rv[2 * p].y, rv[2 * p + 1].x, rv[2 * p + 1].y};   // keys 0-3 | 8-11
+      const u32x4 hi = {rv[2 * p].z, rv[2 * p].w, rv[2 * p + 1].z, rv[2 * p + 1].w};   // keys 4-7 | 12-15
+      sV[buf][vrow * VCPR + (ch ^ sw)] = lo;
+      sV[buf][vrow * VCPR + ((ch + 1) ^ sw)] = hi;
     }
   };
 
@@ -334,112 +369,99 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
 #pragma unroll
       for (int r = 0; r < 16; ++r) o[hb][t][r] = 0.0f;
   float m_run[2] = {-INFINITY, -INFINITY}, l_run[2] = {0.0f, 0.0f};
+  const bf16x2_t ones = {(bf16)1.0f, (bf16)1.0f};
 
   const int key_end = sg.nf == 1 ? sg.n : seg_len;
-  const int ntiles = (key_end + BK - 1) / BK;
+  const int nsteps = (key_end + KS - 1) / KS;
+  const int ntiles = (nsteps + 3) / 4;
   load_tile(0);
   store_tile(0);
   __syncthreads();
-  const bf16x2_t ones = {(bf16)1.0f, (bf16)1.0f};
+  load_tile(ntiles > 1 ? KT : 0);
 
-  for (int it = 0; it < ntiles; ++it) {
-    const int cur = it & 1, kt = it * BK;
-    load_tile(it + 1 < ntiles ? kt + BK : kt);   // unconditional: the registers stay plain values
+  f32x16 s_next[2];
+  qk_step(sK[0], 0, l32, g, qf, s_next);
 
-    const int f0 = kt / sg.npad;
-    const bool full = kt + BK <= (f0 * sg.npad + sg.n) && kt + BK <= key_end;
-    // two 32-key steps per tile: S^T, online softmax and PV per step keep the live registers low
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
-      f32x16 s[2];
-      {
-        const int krow = kb * 32 + l32;
-        u32x4 kf[4];
-#pragma unroll
-        for (int f = 0; f < 4; ++f) kf[f] = sK[cur][krow * CPR + ((2 * f + g) ^ (krow & 7))];
-#pragma unroll
-        for (int hb = 0; hb < 2; ++hb) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) s[hb][r] = 0.0f;
-#pragma unroll
-          for (int f = 0; f < 4; ++f)
-            s[hb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf[f], *(const bf16x8*)&qf[hb][f],
-                                                            s[hb], 0, 0, 0);
-        }
+  for (int st = 0; st < nsteps; ++st) {
+    const int tile = st >> 2, sub = st & 3, cur = tile & 1;
+    const int k0 = st * KS;
+    f32x16 s[2] = {s_next[0], s_next[1]};
+    if (st + 1 < nsteps) {
+      if (sub == 3) {   // the next step is in the next tile: publish it
+        __syncthreads();
+        store_tile(cur ^ 1);
+        __syncthreads();
+        load_tile(tile + 2 < ntiles ? (tile + 2) * KT : 0);
       }
-      if (!full) {   // branch-free select: no divergent control flow around the scores
-        const unsigned bits = key_mask(kt + kb * 32, g, key_end, sg.npad, sg.n);
+      const int nx = st + 1;
+      qk_step(sK[(nx >> 2) & 1], (nx & 3) * KS, l32, g, qf, s_next);
+    }
+    // mask keys outside the segment or in the padding rows between frames
+    const int f0 = k0 / sg.npad;
+    const bool full = k0 + KS <= (f0 * sg.npad + sg.n) && k0 + KS <= key_end;
+    if (!full) {   // branch-free select: no divergent control flow around the scores
+      const unsigned bits = key_mask(k0, g, key_end, sg.npad, sg.n);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const bool ok = (bits >> r) & 1u;
-          s[0][r] = ok ? s[0][r] : -INFINITY;
-          s[1][r] = ok ? s[1][r] : -INFINITY;
-        }
-      }
-      // running max: moved only when a step's max exceeds it by more than 8 (log2 units)
-      float mx[2];
-#pragma unroll
-      for (int hb = 0; hb < 2; ++hb) {
-        float a = s[hb][0];
-#pragma unroll
-        for (int r = 1; r < 16; ++r) a = fmaxf(a, s[hb][r]);
-        a = fmaxf(a, __shfl_xor(a, 32, 64));
-        mx[hb] = a * c;
-      }
-      const bool grow = (mx[0] > m_run[0] + 8.0f) || (mx[1] > m_run[1] + 8.0f);
-      if (__any(grow)) {
-#pragma unroll
-        for (int hb = 0; hb < 2; ++hb) {
-          const float m_new = fmaxf(m_run[hb], mx[hb]);
-          const float alpha = m_new == -INFINITY ? 1.0f : fast_exp2(m_run[hb] - m_new);
-          m_run[hb] = m_new;
-          l_run[hb] *= alpha;
-#pragma unroll
-          for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) o[hb][t][r] *= alpha;
-        }
-      }
-      // probabilities (bf16, B operand of PV) and their row sums
-      bf16x8 pf[2][2];
-#pragma unroll
-      for (int hb = 0; hb < 2; ++hb) {
-        const float nm = -m_run[hb];
-        float ls = 0.0f;
-#pragma unroll
-        for (int j2 = 0; j2 < 2; ++j2) {
-#pragma unroll
-          for (int r = 0; r < 8; ++r) pf[hb][j2][r] = (bf16)fast_exp2(fmaf(s[hb][8 * j2 + r], c, nm));
-#pragma unroll
-          for (int r = 0; r < 8; r += 2) {
-            const bf16x2_t pr = {pf[hb][j2][r], pf[hb][j2][r + 1]};
-            ls = __builtin_amdgcn_fdot2_f32_bf16(pr, ones, ls, false);
-          }
-        }
-        l_run[hb] += ls;
-      }
-      // O^T += V^T P^T for this step's 32 keys; V fragments shared by both query blocks
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int drow = t * 32 + l32;
-        const int sw = drow & 7;
-        const u32x2* row = (const u32x2*)(sV[cur] + drow * CPR);
-#pragma unroll
-        for (int j2 = 0; j2 < 2; ++j2) {
-          const int c0 = 4 * kb + 2 * j2;
-          const u32x2 lo = row[2 * (c0 ^ sw) + g];
-          const u32x2 hi = row[2 * ((c0 + 1) ^ sw) + g];
-          const u32x4 vf = {lo.x, lo.y, hi.x, hi.y};
-#pragma unroll
-          for (int hb = 0; hb < 2; ++hb)
-            o[hb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&vf, pf[hb][j2], o[hb][t], 0, 0, 0);
-        }
+      for (int r = 0; r < 16; ++r) {
+        const bool ok = (bits >> r) & 1u;
+        s[0][r] = ok ? s[0][r] : -INFINITY;
+        s[1][r] = ok ? s[1][r] : -INFINITY;
       }
     }
-    if (it + 1 < ntiles) {
-      __syncthreads();
-      store_tile(cur ^ 1);
-      __syncthreads();
+    // running max: moved only when a step's max exceeds it by more than 8 (log2 units)
+    float mx[2];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      float a = s[hb][0];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) a = fmaxf(a, s[hb][r]);
+      a = fmaxf(a, __shfl_xor(a, 32, 64));
+      mx[hb] = a * c;
+    }
+    const bool grow = (mx[0] > m_run[0] + 8.0f) || (mx[1] > m_run[1] + 8.0f);
+    if (__any(grow)) {
+#pragma unroll
+      for (int hb = 0; hb < 2; ++hb) {
+        const float m_new = fmaxf(m_run[hb], mx[hb]);
+        const float alpha = m_new == -INFINITY ? 1.0f : fast_exp2(m_run[hb] - m_new);
+        m_run[hb] = m_new;
+        l_run[hb] *= alpha;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) o[hb][t][r] *= alpha;
+      }
+    }
+    // probabilities (bf16, B operand of PV) and their row sums
+    u32x4 pf[2][2];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      const float nm = -m_run[hb];
+      float ls = 0.0f;
+#pragma unroll
+      for (int j2 = 0; j2 < 2; ++j2)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const f32x2 e = {fast_exp2(fmaf(s[hb][8 * j2 + 2 * q], c, nm)),
+                           fast_exp2(fmaf(s[hb][8 * j2 + 2 * q + 1], c, nm))};
+          const bf16x2_t pr = __builtin_convertvector(e, bf16x2_t);
+          ls = __builtin_amdgcn_fdot2_f32_bf16(pr, ones, ls, false);
+          pf[hb][j2][q] = __builtin_bit_cast(unsigned, pr);
+        }
+      l_run[hb] += ls;
+    }
+    // O^T += V^T P^T for this step's 32 keys; V fragments shared by both query blocks
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int drow = t * 32 + l32;
+#pragma unroll
+      for (int j2 = 0; j2 < 2; ++j2) {
+        const u32x4 vf = sV[cur][drow * VCPR + ((4 * sub + 2 * j2 + g) ^ (drow & 15))];
+#pragma unroll
+        for (int hb = 0; hb < 2; ++hb)
+          o[hb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&vf, *(const bf16x8*)&pf[hb][j2],
+                                                             o[hb][t], 0, 0, 0);
+      }
     }
   }
 

@@ -45,3 +45,19 @@ template <> MF_DEV bf16 from_f32<bf16>(float x) { return (bf16)x; }
 template <typename T> MF_DEV float to_f32(T x) { return (float)x; }
 
 MF_DEV float gelu_erf(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, formula 7.1.26:
+// erf(x) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-x^2), t = 1 / (1 + p x), x >= 0,
+// |error| <= 1.5e-7.  Used where the result is rounded to bf16 (relative step 2^-8).
+MF_DEV float erf_as7126(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  float poly = fmaf(1.061405429f, t, -1.453152027f);
+  poly = fmaf(poly, t, 1.421413741f);
+  poly = fmaf(poly, t, -0.284496736f);
+  poly = fmaf(poly, t, 0.254829592f);
+  poly *= t;
+  const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
+  return copysignf(fmaf(-poly, e, 1.0f), x);
+}
+MF_DEV float gelu_erf_fast(float z) { return 0.5f * z * (1.0f + erf_as7126(z * 0.70710678118654752f)); }

@@ -2,9 +2,11 @@
 // erf-GELU / scatter into head-major Q, K and transposed V / patch-embedding assembly.
 //
 // Workgroup: 256 threads = 2 x 2 waves; each wave owns a (32 WM) x (32 WN) block of 32x32
-// MFMA tiles.  A and Bt tiles are staged through LDS in 128-byte k-slices (64 bf16 or
-// 32 fp32 per row), double-buffered, with the 16-byte chunks of each row XOR-swizzled by the
-// row index so that the per-lane 16-byte fragment reads are conflict free.
+// MFMA tiles (256 x 128 tiles of 128 x 64 per wave for large grids, else 128 x 128).  A and Bt
+// tiles are staged through one LDS stage in 128-byte k-slices (64 bf16 or 32 fp32 per row)
+// while the next slice is prefetched into registers; the 16-byte chunks of each row are
+// XOR-swizzled by (row >> 1) & 7 so that the 16 lanes of a fragment read cover 16 distinct
+// 16-byte slots (measured conflict-free on gfx950).
 //   bf16: v_mfma_f32_32x32x16_bf16, one 16-byte fragment (8 k) per lane per MFMA
 //   fp32: v_mfma_f32_32x32x2_f32, the same 16-byte fragment feeds 4 MFMAs
 // A and B use the same (lane group, register) -> k assignment, so the contraction is
@@ -29,24 +31,16 @@ template <> struct Mma<float> {
   }
 };
 
-// EPI_QKV: n is the column within the q, k or v block (qkv_which 0, 1, 2) and dst that block.
+// Element epilogues of the GELU / STORE / PATCH kinds (RESID and QKV are vectorised in the kernel).
 template <typename T, int EPI>
-MF_DEV void epilogue(const GemmArgs& a, int m, int n, float v, int qkv_which = 0, T* dst = nullptr) {
-  if (a.bias && EPI != EPI_PATCH && EPI != EPI_QKV) v += a.bias[n];
-  if constexpr (EPI == EPI_RESID) {
-    float* c = (float*)a.C + (int64_t)m * a.ldc + n;
-    *c += v;
-  } else if constexpr (EPI == EPI_GELU) {
-    ((T*)a.C)[(int64_t)m * a.ldc + n] = from_f32<T>(gelu_erf(v));
+MF_DEV void epilogue(const GemmArgs& a, int m, int n, float v) {
+  if (a.bias && EPI != EPI_PATCH) v += a.bias[n];
+  if constexpr (EPI == EPI_GELU) {
+    // bf16 outputs take the 1.5e-7-accurate rational erf; fp32 outputs the library erff
+    if constexpr (sizeof(T) == 2) ((T*)a.C)[(int64_t)m * a.ldc + n] = from_f32<T>(gelu_erf_fast(v));
+    else ((T*)a.C)[(int64_t)m * a.ldc + n] = from_f32<T>(gelu_erf(v));
   } else if constexpr (EPI == EPI_STORE) {
     ((T*)a.C)[(int64_t)m * a.ldc + n] = from_f32<T>(v);
-  } else if constexpr (EPI == EPI_QKV) {
-    // which (q, k or v) is uniform over the tile: the caller passes it resolved, with dst
-    const int h = n / a.hd, d = n - h * a.hd;
-    if (qkv_which < 2)
-      dst[((int64_t)h * a.mpad + m) * a.hd + d] = from_f32<T>(v);
-    else
-      dst[((int64_t)h * a.hd + d) * a.mpad + m] = from_f32<T>(v);
   } else if constexpr (EPI == EPI_PATCH) {
     // rowinfo: bits 30-31 kind (0 patch, 1 reference camera, 2 other camera, 3 gap), low bits PE row
     const int32_t ri = a.rowinfo[m];
@@ -60,7 +54,11 @@ MF_DEV void epilogue(const GemmArgs& a, int m, int n, float v, int qkv_which = 0
   }
 }
 
-template <typename T, int WM, int WN, int EPI>
+// TC = 1 computes each 32x32 tile transposed (the weight fragment as the MFMA's A operand), so
+// that a lane holds one output row and 4 consecutive columns per register group: every
+// epilogue access is a 16-byte (fp32) or 8-byte (bf16) vector.  TC = 0 (lane = one column, 4
+// consecutive rows per group) is used for the transposed V store of the QKV projection.
+template <typename T, int WM, int WN, int EPI, int TC>
 __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   constexpr int BM = 64 * WM, BN = 64 * WN;
   constexpr int EPC = 16 / sizeof(T);   // elements per 16-byte chunk
@@ -90,13 +88,13 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
     const int c = tid + i * 256, row = c >> 3, col = c & 7;
     const int gm = min(m0 + row, a.M - 1);
     aptr[i] = A + (int64_t)gm * a.lda + col * EPC;
-    aoff[i] = row * 8 + (col ^ (row & 7));
+    aoff[i] = row * 8 + (col ^ ((row >> 1) & 7));
   }
 #pragma unroll
   for (int i = 0; i < BCH; ++i) {
     const int c = tid + i * 256, row = c >> 3, col = c & 7;
     bptr[i] = B + (int64_t)(n0 + row) * a.ldb + col * EPC;
-    boff[i] = row * 8 + (col ^ (row & 7));
+    boff[i] = row * 8 + (col ^ ((row >> 1) & 7));
   }
 
   f32x16 acc[WM][WN];
@@ -134,17 +132,20 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
         const int row = wr * 32 * WM + i * 32 + l32;
-        fa[i] = sA[row * 8 + (ch ^ (row & 7))];
+        fa[i] = sA[row * 8 + (ch ^ ((row >> 1) & 7))];
       }
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         const int row = wc * 32 * WN + j * 32 + l32;
-        fb[j] = sB[row * 8 + (ch ^ (row & 7))];
+        fb[j] = sB[row * 8 + (ch ^ ((row >> 1) & 7))];
       }
 #pragma unroll
       for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) Mma<T>::run(fa[i], fb[j], acc[i][j]);
+        for (int j = 0; j < WN; ++j) {
+          if constexpr (TC) Mma<T>::run(fb[j], fa[i], acc[i][j]);
+          else Mma<T>::run(fa[i], fb[j], acc[i][j]);
+        }
     }
     __syncthreads();
   }
@@ -155,36 +156,132 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   T* dst = nullptr;
   if constexpr (EPI == EPI_QKV) {
     const int D = a.heads * a.hd;
-    which = n0 / D;
-    nbase = which * D;
+    which = a.qkv_which0 + n0 / D;
+    nbase = (n0 / D) * D;
     dst = (T*)(which == 0 ? a.q : (which == 1 ? a.k : a.vt));
   }
+  if constexpr (TC) {
+    // lane (l32, g) of tile (i, j): row m, columns nb + 8 rg + e (rg, e < 4)
 #pragma unroll
-  for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i) {
+      const int m = m0 + wr * 32 * WM + i * 32 + l32;
+      if (m >= a.M) continue;
+      int32_t ri = 0;
+      if constexpr (EPI == EPI_PATCH) ri = a.rowinfo[m];
 #pragma unroll
-    for (int j = 0; j < WN; ++j) {
-      const int n = n0 + wc * 32 * WN + j * 32 + l32;
+      for (int j = 0; j < WN; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = m0 + wr * 32 * WM + i * 32 + 8 * (r >> 2) + 4 * g + (r & 3);
-        if (m < a.M) {
-          if constexpr (EPI == EPI_QKV) {
-            const float v = acc[i][j][r] + a.bias[n];
-            epilogue<T, EPI>(a, m, n - nbase, v, which, dst);
+        for (int rg = 0; rg < 4; ++rg) {
+          const int n = n0 + wc * 32 * WN + j * 32 + 4 * g + 8 * rg;
+          f32x4 v = {acc[i][j][4 * rg], acc[i][j][4 * rg + 1], acc[i][j][4 * rg + 2], acc[i][j][4 * rg + 3]};
+          if constexpr (EPI != EPI_PATCH) {
+            if (a.bias) v += *(const f32x4*)(a.bias + n);
+          }
+          if constexpr (EPI == EPI_RESID) {
+            f32x4* c = (f32x4*)((float*)a.C + (int64_t)m * a.ldc + n);
+            *c = *c + v;
+          } else if constexpr (EPI == EPI_PATCH) {
+            // rowinfo bits 30-31: 0 patch, 1 reference camera, 2 other camera, 3 padding
+            const int kind = (ri >> 30) & 3;
+            f32x4 o;
+            if (kind == 0) o = v + *(const f32x4*)(a.bias + n) + *(const f32x4*)(a.pe + (int64_t)(ri & 0x3fffffff) * a.N + n);
+            else if (kind == 1) o = *(const f32x4*)(a.c_ref + n);
+            else if (kind == 2) o = *(const f32x4*)(a.c_other + n);
+            else o = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+            *(f32x4*)((float*)a.C + (int64_t)m * a.ldc + n) = o;
           } else {
-            epilogue<T, EPI>(a, m, n, acc[i][j][r]);
+            if constexpr (EPI == EPI_GELU) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) v[e] = sizeof(T) == 2 ? gelu_erf_fast(v[e]) : gelu_erf(v[e]);
+            }
+            T* out;
+            if constexpr (EPI == EPI_QKV) {
+              const int nn = n - nbase;
+              const int h = nn / a.hd, d = nn - h * a.hd;
+              out = dst + ((int64_t)h * a.mpad + m) * a.hd + d;
+            } else {
+              out = (T*)a.C + (int64_t)m * a.ldc + n;
+            }
+            if constexpr (sizeof(T) == 2) {
+              bf16x4 b;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) b[e] = (bf16)v[e];
+              *(bf16x4*)out = b;
+            } else {
+              *(f32x4*)out = v;
+            }
+          }
+        }
+    }
+  } else {
+    // lane (l32, g) of tile (i, j): column n, rows mb + 8 rg + e
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int n = n0 + wc * 32 * WN + j * 32 + l32;
+        const int mb = m0 + wr * 32 * WM + i * 32 + 4 * g;
+        if constexpr (EPI == EPI_QKV) {
+          const int nn = n - nbase;
+          const int h = nn / a.hd, d = nn - h * a.hd;
+          const float bn = a.bias[n];
+          if (which < 2) {
+            T* col = dst + (int64_t)h * a.mpad * a.hd + d;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int m = mb + 8 * (r >> 2) + (r & 3);
+              if (m < a.M) col[(int64_t)m * a.hd] = from_f32<T>(acc[i][j][r] + bn);
+            }
+          } else {
+            // V^T: the four rows of a register group are consecutive keys -> one vector store
+            T* row = dst + ((int64_t)h * a.hd + d) * a.mpad;
+#pragma unroll
+            for (int rg = 0; rg < 4; ++rg) {
+              const int m = mb + 8 * rg;
+              if (m + 3 < a.M) {
+                if constexpr (sizeof(T) == 2) {
+                  bf16x4 v;
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) v[e] = (bf16)(acc[i][j][4 * rg + e] + bn);
+                  *(bf16x4*)(row + m) = v;
+                } else {
+                  f32x4 v;
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * rg + e] + bn;
+                  *(f32x4*)(row + m) = v;
+                }
+              } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  if (m + e < a.M) row[m + e] = from_f32<T>(acc[i][j][4 * rg + e] + bn);
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int m = mb + 8 * (r >> 2) + (r & 3);
+            if (m < a.M) epilogue<T, EPI>(a, m, n, acc[i][j][r]);
           }
         }
       }
-    }
+  }
 }
 
-template <typename T, int EPI, int WM, int WN>
+template <typename T, int EPI, int WM, int WN, int TC>
 static hipError_t launch_tile(const GemmArgs& a, hipStream_t s) {
   constexpr int BM = 64 * WM, BN = 64 * WN;
+  if (a.M <= 0 || a.N <= 0) return hipSuccess;
   const int nb = ((a.M + BM - 1) / BM) * (a.N / BN);
-  hipLaunchKernelGGL((gemm_kernel<T, WM, WN, EPI>), dim3(nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((gemm_kernel<T, WM, WN, EPI, TC>), dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int EPI, int TC>
+static hipError_t launch_shape(const GemmArgs& a, hipStream_t s) {
+  // 256 x 128 tiles (waves of 128 x 64: fewer LDS bytes per MFMA) once there are enough of them
+  if (sizeof(T) == 2 && (int64_t)((a.M + 255) / 256) * (a.N / 128) >= 512) return launch_tile<T, EPI, 4, 2, TC>(a, s);
+  return launch_tile<T, EPI, 2, 2, TC>(a, s);
 }
 
 template <typename T, int EPI>
@@ -192,10 +289,24 @@ static hipError_t launch(const GemmArgs& a, hipStream_t s) {
   constexpr int BK = 128 / sizeof(T);
   if (a.M <= 0) return hipSuccess;
   if (a.N % 128 != 0 || a.K % BK != 0 || a.K <= 0) return hipErrorInvalidValue;
-  if (EPI == EPI_QKV && ((a.heads * a.hd) % 128 != 0 || !a.bias)) return hipErrorInvalidValue;
-  // 256 x 128 tiles (waves of 128 x 64: fewer LDS bytes per MFMA) once there are enough of them
-  if (sizeof(T) == 2 && (int64_t)((a.M + 255) / 256) * (a.N / 128) >= 512) return launch_tile<T, EPI, 4, 2>(a, s);
-  return launch_tile<T, EPI, 2, 2>(a, s);
+  if constexpr (EPI == EPI_QKV) {
+    const int D = a.heads * a.hd;
+    if (D % 128 != 0 || a.N != 3 * D || !a.bias || a.hd % 4 != 0) return hipErrorInvalidValue;
+    // q and k columns (row-contiguous stores) transposed tiles; v columns (V^T stores) plain
+    GemmArgs qk = a;
+    qk.N = 2 * D;
+    qk.qkv_which0 = 0;
+    hipError_t e = launch_shape<T, EPI, 1>(qk, s);
+    if (e != hipSuccess) return e;
+    GemmArgs v = a;
+    v.N = D;
+    v.Bt = (const T*)a.Bt + (int64_t)2 * D * a.ldb;
+    v.bias = a.bias + 2 * D;
+    v.qkv_which0 = 2;
+    return launch_shape<T, EPI, 0>(v, s);
+  } else {
+    return launch_shape<T, EPI, 1>(a, s);
+  }
 }
 
 template <typename T>

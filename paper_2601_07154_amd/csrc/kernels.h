@@ -18,6 +18,7 @@ struct GemmArgs {
   void* C; int64_t ldc;            // RESID: fp32 [M,N] (+=); GELU/STORE: dtype [M,N]; PATCH: fp32 X
   // EPI_QKV: Q, K head-major [H][mpad][hd], V transposed [H][hd][mpad]
   void* q; void* k; void* vt; int heads; int hd; int64_t mpad;
+  int qkv_which0;                  // block (0 q, 1 k, 2 v) of column 0 of this launch (set internally)
   // EPI_PATCH: per-row kind/PE row (rowinfo), PE table [rows][N] fp32, camera tokens
   const int32_t* rowinfo; const float* pe; const float* c_ref; const float* c_other;
 };
