@@ -113,6 +113,58 @@ def cpu_baseline(wl, sigma: float):
     return fps, dt, out
 
 
+def run_serve(args):
+    """Serving workload: streams of uneven lengths and resolutions ({280, 378, 504} x 504), Poisson
+    arrivals, window 16 stride 8, the 24-layer D=1024 model in BF16 on the threaded engine, against
+    the plain FP32 single-stream path (one stream at a time, one window per batch)."""
+    import torch
+    import paper_2601_07154_amd as mfp
+    from paper_2601_07154_amd import serving
+    model = mf_synth.SERVE_MODEL
+    blob = mf_synth.make_weights(model, 0)
+    raw = mf_synth.serve_streams(args.serve_streams, seed=5, min_len=60, max_len=args.serve_max_len,
+                                 rate=args.serve_rate)
+    specs = [serving.StreamSpec(a if args.serve_paced else 0.0, n, H, W, seed) for (a, n, H, W, seed) in raw]
+    pools = {}
+
+    def pool(H, W):
+        if (H, W) not in pools:
+            pools[(H, W)] = torch.from_numpy(mf_synth.make_frames(16, H, W, 7000 + H)).cuda()
+        return pools[(H, W)]
+
+    K = lambda H, W: (0.8 * W, 0.8 * W, W / 2.0, H / 2.0)
+    rows = mfp.rows_per_frame(504, 504)
+    eng = mfp.Engine.from_model(model, blob, precision="bf16", threaded=True, max_tokens=6 * 16 * rows)
+    out = serving.serve(eng, specs, pool, 16, 8, K, fps=30.0, paced=args.serve_paced, time_limit=900)
+    st = eng.stats()
+    eng.close()
+    lat = serving.latency_summary(out["records"])
+    frames = lat["frames"]
+    res = {"metric": "serving frames/sec and per-frame latency (BF16, continuous batching) vs FP32 single-stream",
+           "value": frames / out["wall"], "unit": "frames/s", "n_gpus": 1, "dtype": "bf16",
+           "regime": "paced 30 fps, Poisson arrivals" if args.serve_paced else "throughput (all frames available)",
+           "streams": len(specs), "frames": frames, "wall_s": out["wall"], "latency_ms": lat,
+           "batches": st["batches_run"], "windows": st["windows_run"], "gpu_ms": st["gpu_ms"],
+           "config": {"workload": "serving", "model": "24L D1024 16 heads MLP 4096", "window": 16, "overlap": 8,
+                      "lengths": f"U[60, {args.serve_max_len}]", "resolutions": "{280,378,504}x504",
+                      "rate_per_s": args.serve_rate}}
+    if args.serve_fp32_streams:
+        eng = mfp.Engine.from_model(model, blob, precision="fp32", threaded=True, max_tokens=16 * rows)
+        sub = [serving.StreamSpec(0.0, sp.length, sp.height, sp.width) for sp in specs[:args.serve_fp32_streams]]
+        t_frames, t_wall, lats = 0, 0.0, []
+        for sp in sub:                      # one stream at a time, one window per batch
+            o = serving.serve(eng, [sp], pool, 16, 8, K, paced=False, time_limit=900)
+            t_frames += len(o["records"][0])
+            t_wall += o["wall"]
+            lats.append(o["records"][0])
+        eng.close()
+        fl = serving.latency_summary(lats)
+        res["fp32_single_stream"] = {"value": t_frames / t_wall, "unit": "frames/s", "streams": len(sub),
+                                     "latency_ms": fl}
+        res["speedup_vs_fp32_single_stream"] = res["value"] / res["fp32_single_stream"]["value"]
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,10 +177,19 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (an elementwise torch kernel) so that HBM counters "
                          "of the same profiler run can be scaled by a transfer of known size")
+    ap.add_argument("--serve", action="store_true", help="run the serving workload instead (separate JSON line)")
+    ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-max-len", type=int, default=160)
+    ap.add_argument("--serve-rate", type=float, default=0.4)
+    ap.add_argument("--serve-paced", action="store_true")
+    ap.add_argument("--serve-fp32-streams", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
+    if args.serve:
+        run_serve(args)
+        return
     wl = mf_synth.SMALL
     if args.copy_calibration:
         import torch

@@ -85,6 +85,8 @@ def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float
                 if rc == MF_EAGAIN:
                     break
                 st.pushed += n
+        if not getattr(engine, "threaded", True):
+            engine.step()
         # polls
         for st in list(active):
             r, rc = engine.poll(st.sid, poll_cap)
