@@ -41,6 +41,8 @@ typedef int32_t mf_status;
 /* precisions of the ViT forward (the chaining and focus stages are always FP64) */
 #define MF_FP32 0       /* fp32 operands on fp32 MFMA */
 #define MF_BF16 1       /* bf16 GEMM/attention operands, fp32 accumulation/softmax/LayerNorm */
+#define MF_FP8 2        /* as MF_BF16, but the QKV and MLP GEMMs take OCP E4M3 operands: weights with
+                           static per-tensor scales, activations with dynamic per-window scales */
 
 /* anchoring modes */
 #define MF_ANCHOR_YAW 0 /* lock pitch and roll, propagate yaw and translation (the paper) */
@@ -59,7 +61,7 @@ typedef struct mf_model_cfg {
   int32_t heads;      /* D / heads must be 32 or 64 */
   int32_t mlp;        /* MLP hidden width (multiple of 128) */
   int32_t patch;      /* must be 14 */
-  int32_t precision;  /* MF_FP32 or MF_BF16 */
+  int32_t precision;  /* MF_FP32, MF_BF16 or MF_FP8 */
 } mf_model_cfg;
 
 typedef struct mf_runtime_cfg {

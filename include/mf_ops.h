@@ -57,6 +57,27 @@ mf_status mf_op_attention(int32_t precision, int32_t head_dim, int32_t heads, in
 mf_status mf_op_gemm(int32_t precision, const void* A, const void* Bt, const float* bias, float* C,
                      int32_t M, int32_t N, int32_t K, void* stream);
 
+/* Low-precision variant of the window inference (the foundation-model stage of Sec. 2.2, which
+ * the paper runs without fixing a precision): OCP E4M3 operands with per-tensor scales.
+ *
+ * FP8 GEMM: C[M][N] = (A[M][K] Bt[N][K]^T) * ascale[m] * bscale[0] + bias, fp32 out (bias nullable).
+ * A, Bt: E4M3 bytes, device; ascale [M], bscale [1] fp32 device; N % 128 == 0, K % 128 == 0.
+ * MF_EINVAL on other shapes or null operands; MF_EDEVICE on a launch error. */
+mf_status mf_op_gemm_fp8(const void* A, const void* Bt, const float* ascale, const float* bscale, const float* bias,
+                         float* C, int32_t M, int32_t N, int32_t K, void* stream);
+
+/* q[i] = E4M3(x[i] * (1/scale)) (fp32 product), round to nearest even, saturating at +-448;
+ * x fp32 device, q n bytes device, n % 4 == 0, scale > 0. */
+mf_status mf_op_quantize_fp8(const float* x, int64_t n, float scale, void* q, void* stream);
+
+/* Per-window dynamic activation scaling: for each window w of segs (host, nwin rows of
+ * {base, nf, n, npad} as for attention), s_w = amax / 448 over the valid rows (the first n of
+ * every npad) of y [rows][C] bf16 (s_w = 1 for an all-zero window); every row r of the window,
+ * padding included, gets q[r][c] = E4M3(y[r][c] * (1/s_w)) and srow[r] = s_w.  y, q ([rows][C]
+ * bytes), srow ([rows] fp32): device.  C % 16 == 0; windows must not overlap. */
+mf_status mf_op_quantize_fp8_windows(const void* y, int32_t C, const int32_t* segs, int32_t nwin, void* q,
+                                     float* srow, void* stream);
+
 /* y = LayerNorm(x) * g + b over rows of dim (eps 1e-6), x fp32, y in the precision's type. */
 mf_status mf_op_layernorm(int32_t precision, const float* x, void* y, const float* g, const float* b,
                           int64_t rows, int32_t dim, void* stream);

@@ -16,6 +16,12 @@ Options
                     the PV product) rounded to bfloat16 RNE, accumulation in
                     float64: an emulation that calibrates how much a bf16 path
                     is expected to deviate; it is not a parity reference.
+  precision="fp8"   as "bf16", except that the QKV, fc1 and fc2 products take
+                    OCP E4M3 operands: the bf16-rounded activations of the whole
+                    window and each weight matrix are divided by their own
+                    per-tensor scale amax/448, rounded to E4M3 (nearest even,
+                    saturating), and the product is multiplied back by both
+                    scales.  Also a calibration, not a parity reference.
 """
 from __future__ import annotations
 
@@ -38,17 +44,50 @@ def round_bf16(x: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+E4M3_MAX = 448.0          # largest finite OCP E4M3 value, 1.75 * 2^8
+E4M3_MIN_NORMAL = 2.0 ** -6
+E4M3_MANT_BITS = 3
+
+
+def round_e4m3(x: np.ndarray) -> np.ndarray:
+    """Round to the nearest OCP E4M3 value (ties to even), saturating at +-448; float64 out.
+
+    Normal binade [2^e, 2^(e+1)), e >= -6, has spacing 2^(e-3); below 2^-6 the subnormals have
+    the fixed spacing 2^-9."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.minimum(np.abs(x), E4M3_MAX)
+    e = np.floor(np.log2(np.maximum(a, E4M3_MIN_NORMAL)))
+    quantum = 2.0 ** (e - E4M3_MANT_BITS)
+    r = np.round(a / quantum) * quantum        # numpy rounds halves to even
+    return np.copysign(np.minimum(r, E4M3_MAX), x)
+
+
+def quantise_e4m3(x: np.ndarray) -> tuple[np.ndarray, float]:
+    """Per-tensor scaling: s = amax / 448 (1 for an all-zero tensor), q = E4M3(x / s); returns (q, s)."""
+    amax = float(np.max(np.abs(x))) if np.size(x) else 0.0
+    s = amax / E4M3_MAX if amax > 0.0 else 1.0
+    return round_e4m3(np.asarray(x, dtype=np.float64) / s), s
+
+
 class Prec:
     def __init__(self, precision: str = "fp64"):
-        if precision not in ("fp64", "bf16"):
+        if precision not in ("fp64", "bf16", "fp8"):
             raise ValueError(precision)
         self.name = precision
 
     def op(self, x):
-        return round_bf16(x) if self.name == "bf16" else x
+        return x if self.name == "fp64" else round_bf16(x)
 
     def matmul(self, a, b):
         return self.op(a) @ self.op(b)
+
+    def matmul_q(self, a, b):
+        """Products that the fp8 mode runs on E4M3 operands (QKV, fc1, fc2)."""
+        if self.name != "fp8":
+            return self.matmul(a, b)
+        qa, sa = quantise_e4m3(round_bf16(a))
+        qb, sb = quantise_e4m3(b)
+        return (qa @ qb) * (sa * sb)
 
 
 # ----------------------------------------------------------------------------- weights
@@ -154,7 +193,7 @@ def multihead(xn: np.ndarray, lw: dict, heads: int, groups: list, prec: Prec) ->
     """
     T, D = xn.shape
     hd = D // heads
-    qkv = prec.matmul(xn, lw["W_qkv"]) + lw["b_qkv"]
+    qkv = prec.matmul_q(xn, lw["W_qkv"]) + lw["b_qkv"]
     q, k, v = qkv[:, :D], qkv[:, D:2 * D], qkv[:, 2 * D:]
     o = np.empty((T, D), dtype=np.float64)
     for (s, n) in groups:
@@ -167,8 +206,8 @@ def multihead(xn: np.ndarray, lw: dict, heads: int, groups: list, prec: Prec) ->
 def block(x: np.ndarray, lw: dict, heads: int, groups: list, prec: Prec) -> np.ndarray:
     """One pre-LN transformer block: X += Attn(LN1 X); X += W2 GELU(W1 LN2 X)."""
     x = x + multihead(layer_norm(x, lw["ln1_g"], lw["ln1_b"]), lw, heads, groups, prec)
-    h = gelu(prec.matmul(layer_norm(x, lw["ln2_g"], lw["ln2_b"]), lw["W_1"]) + lw["b_1"])
-    return x + prec.matmul(h, lw["W_2"]) + lw["b_2"]
+    h = gelu(prec.matmul_q(layer_norm(x, lw["ln2_g"], lw["ln2_b"]), lw["W_1"]) + lw["b_1"])
+    return x + prec.matmul_q(h, lw["W_2"]) + lw["b_2"]
 
 
 def embed(frames: np.ndarray, w: dict, patch: int = 14, prec: Prec | None = None) -> np.ndarray:

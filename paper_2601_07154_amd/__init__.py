@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (FOCUS_DTYPE, MF_ANCHOR_SE3, MF_ANCHOR_YAW, MF_BF16, MF_DEVICE_PTR, MF_EAGAIN, MF_ECLOSED,
                    MF_EOS, MF_FP32, MF_OK, MF_POSES_LOCAL)
 
-PRECISIONS = {"fp32": MF_FP32, "bf16": MF_BF16}
+PRECISIONS = {"fp32": MF_FP32, "bf16": MF_BF16, "fp8": _lib.MF_FP8}
 
 
 class MfError(RuntimeError):
@@ -199,3 +199,27 @@ def op_layernorm(precision: str, x, y, g, b, stream: int = 0):
     lib = _lib.lib()
     _check(lib.mf_op_layernorm(PRECISIONS[precision], _ptr(x)[0], _ptr(y)[0], _ptr(g)[0], _ptr(b)[0], rows, dim,
                                C.c_void_p(stream)), "mf_op_layernorm")
+
+
+def op_gemm_fp8(A8, Bt8, ascale, bscale, bias, Cout, stream: int = 0):
+    """A8 [M][K], Bt8 [N][K]: uint8 tensors of E4M3 bytes; ascale [M], bscale [1] float32 (device)."""
+    M, K = A8.shape
+    N = Bt8.shape[0]
+    lib = _lib.lib()
+    _check(lib.mf_op_gemm_fp8(_ptr(A8)[0], _ptr(Bt8)[0], _ptr(ascale)[0], _ptr(bscale)[0],
+                              _ptr(bias)[0] if bias is not None else None, _ptr(Cout)[0], M, N, K,
+                              C.c_void_p(stream)), "mf_op_gemm_fp8")
+
+
+def op_quantize_fp8(x, scale: float, q, stream: int = 0):
+    lib = _lib.lib()
+    _check(lib.mf_op_quantize_fp8(_ptr(x)[0], x.numel(), scale, _ptr(q)[0], C.c_void_p(stream)),
+           "mf_op_quantize_fp8")
+
+
+def op_quantize_fp8_windows(y, segs, q, srow, stream: int = 0):
+    """y [rows][C] bfloat16 (device); segs [nwin][4] {base, nf, n, npad}; q uint8 [rows][C], srow float32 [rows]."""
+    s = np.ascontiguousarray(segs, dtype=np.int32).reshape(-1, 4)
+    lib = _lib.lib()
+    _check(lib.mf_op_quantize_fp8_windows(_ptr(y)[0], y.shape[1], C.c_void_p(s.ctypes.data), s.shape[0], _ptr(q)[0],
+                                          _ptr(srow)[0], C.c_void_p(stream)), "mf_op_quantize_fp8_windows")

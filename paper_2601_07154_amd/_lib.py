@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmfocus.so")
 
 MF_OK, MF_EINVAL, MF_ENOMEM, MF_EAGAIN, MF_ECLOSED, MF_EDEVICE, MF_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-MF_FP32, MF_BF16 = 0, 1
+MF_FP32, MF_BF16, MF_FP8 = 0, 1, 2
 MF_ANCHOR_YAW, MF_ANCHOR_SE3 = 0, 1
 MF_EOS, MF_DEVICE_PTR, MF_POSES_LOCAL = 1, 2, 4
 
@@ -93,6 +93,11 @@ EXPORTS = {
                                     C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
     "mf_op_gemm": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                C.c_int32, C.c_int32, C.c_void_p]),
+    "mf_op_gemm_fp8": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+    "mf_op_quantize_fp8": (C.c_int32, [C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p]),
+    "mf_op_quantize_fp8_windows": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                               C.c_void_p, C.c_void_p]),
     "mf_op_layernorm": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_int32, C.c_void_p]),
 }

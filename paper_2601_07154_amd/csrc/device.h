@@ -4,6 +4,8 @@
 #include <stdint.h>
 
 typedef __bf16 bf16;
+typedef unsigned char fp8;   // OCP E4M3 storage byte
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));

@@ -31,7 +31,7 @@ static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct LayerW {
   const float *ln1_g, *ln1_b, *b_qkv, *b_o, *ln2_g, *ln2_b, *b_1, *b_2;
-  void *Wqkv, *Wo, *W1, *W2;       // transposed [out][in], dtype
+  void *Wqkv, *Wo, *W1, *W2;       // transposed [out][in], compute type (E4M3 bytes for Wqkv/W1/W2 in fp8 mode)
 };
 
 struct Plan {                      // host-side tables of one batch
@@ -51,13 +51,18 @@ class HipExecutor : public Executor {
                  std::string& err) override {
     m_ = m;
     if (m.patch != 14) { err = "patch must be 14"; return MF_EINVAL; }
-    if (m.precision != MF_FP32 && m.precision != MF_BF16) { err = "precision must be MF_FP32 or MF_BF16"; return MF_EINVAL; }
+    if (m.precision != MF_FP32 && m.precision != MF_BF16 && m.precision != MF_FP8) {
+      err = "precision must be MF_FP32, MF_BF16 or MF_FP8";
+      return MF_EINVAL;
+    }
     if (m.depth < 1 || m.heads < 1 || m.dim % m.heads) { err = "bad depth/heads/dim"; return MF_EINVAL; }
     D_ = m.dim; H_ = m.heads; hd_ = D_ / H_; F_ = m.mlp; depth_ = m.depth;
     if (!(D_ == 128 || D_ == 256 || D_ == 384 || D_ == 512 || D_ == 768 || D_ == 1024)) { err = "dim must be one of 128, 256, 384, 512, 768, 1024"; return MF_EINVAL; }
     if (hd_ != 32 && hd_ != 64) { err = "head dim must be 32 or 64"; return MF_EINVAL; }
     if (F_ <= 0 || F_ % 128) { err = "mlp must be a positive multiple of 128"; return MF_EINVAL; }
-    dt_ = m.precision == MF_BF16 ? DT_BF16 : DT_F32;
+    // MF_FP8: the QKV and MLP GEMMs take E4M3 operands; everything else runs as in MF_BF16
+    fp8_ = m.precision == MF_FP8;
+    dt_ = m.precision == MF_FP32 ? DT_F32 : DT_BF16;
     es_ = dt_ == DT_BF16 ? 2 : 4;
     qt_ = attention_q_tile(dt_, hd_);
     const size_t want = expected_floats();
@@ -405,7 +410,8 @@ class HipExecutor : public Executor {
   }
   uint64_t workspace_bytes() const {
     const uint64_t D = D_, wide = std::max<int64_t>(F_, KP);
-    return (uint64_t)mcap_ * (D * 4 + D * es_ + D * es_ + wide * es_ + 4) + (uint64_t)mpad_ * 3 * D * es_ +
+    const uint64_t f8 = fp8_ ? (uint64_t)mcap_ * (D + F_ + 8) : 0;
+    return f8 + (uint64_t)mcap_ * (D * 4 + D * es_ + D * es_ + wide * es_ + 4) + (uint64_t)mpad_ * 3 * D * es_ +
            (uint64_t)fcap_ * (2 * D * 4 + 9 * 4 + 16 * 8 + sizeof(mf_focus) * 2 + 8) + (64u << 20);
   }
 
@@ -422,6 +428,10 @@ class HipExecutor : public Executor {
     HIPCHECK(hipMemsetAsync(Wp_, 0, D * KP * es_, st_));
     HIPCHECK(convert_transpose(dt_, Wp, 588, (int)D, Wp_, KP, st_));
     layers_.resize(depth_);
+    if (fp8_) {
+      HIPCHECK(hipMalloc(&wscale_, (size_t)depth_ * 3 * sizeof(float)));
+      HIPCHECK(hipMalloc(&wamax_, 64));
+    }
     for (int l = 0; l < depth_; ++l) {
       LayerW& L = layers_[l];
       L.ln1_g = take(D); L.ln1_b = take(D);
@@ -434,10 +444,19 @@ class HipExecutor : public Executor {
       L.b_1 = take(F);
       const float* W2 = take(F * D);
       L.b_2 = take(D);
-      HIPCHECK(hipMalloc(&L.Wqkv, 3 * D * D * es_));
+      const size_t ws = fp8_ ? 1 : es_;
+      HIPCHECK(hipMalloc(&L.Wqkv, 3 * D * D * ws));
       HIPCHECK(hipMalloc(&L.Wo, D * D * es_));
-      HIPCHECK(hipMalloc(&L.W1, D * F * es_));
-      HIPCHECK(hipMalloc(&L.W2, F * D * es_));
+      HIPCHECK(hipMalloc(&L.W1, D * F * ws));
+      HIPCHECK(hipMalloc(&L.W2, F * D * ws));
+      if (fp8_) {
+        float* sc = wscale_ + 3 * l;
+        HIPCHECK(quantize_weight_fp8(Wqkv, (int)D, (int)(3 * D), (unsigned char*)L.Wqkv, (int)D, wamax_, sc, st_));
+        HIPCHECK(quantize_weight_fp8(W1, (int)D, (int)F, (unsigned char*)L.W1, (int)D, wamax_, sc + 1, st_));
+        HIPCHECK(quantize_weight_fp8(W2, (int)F, (int)D, (unsigned char*)L.W2, (int)F, wamax_, sc + 2, st_));
+        HIPCHECK(convert_transpose(dt_, Wo, (int)D, (int)D, L.Wo, (int)D, st_));
+        continue;
+      }
       HIPCHECK(convert_transpose(dt_, Wqkv, (int)D, (int)(3 * D), L.Wqkv, (int)D, st_));
       HIPCHECK(convert_transpose(dt_, Wo, (int)D, (int)D, L.Wo, (int)D, st_));
       HIPCHECK(convert_transpose(dt_, W1, (int)D, (int)F, L.W1, (int)D, st_));
@@ -472,6 +491,13 @@ class HipExecutor : public Executor {
     HIPCHECK(hipMemsetAsync(Y_, 0, (size_t)mcap_ * D * es_, st_));
     HIPCHECK(hipMemsetAsync(O_, 0, (size_t)mcap_ * D * es_, st_));
     HIPCHECK(hipStreamSynchronize(st_));
+    if (fp8_) {
+      HIPCHECK(hipMalloc(&Y8_, (size_t)mcap_ * D));
+      HIPCHECK(hipMalloc(&H8_, (size_t)mcap_ * F_));
+      HIPCHECK(hipMalloc(&srow_, (size_t)mcap_ * 4));
+      HIPCHECK(hipMalloc(&srow2_, (size_t)mcap_ * 4));
+      HIPCHECK(hipMalloc(&amax_, (size_t)fcap_ * 4));
+    }
     HIPCHECK(hipMalloc(&camln_, (size_t)fcap_ * D * 4));
     HIPCHECK(hipMalloc(&camg_, (size_t)fcap_ * D * 4));
     HIPCHECK(hipMalloc(&pose9_, (size_t)fcap_ * 9 * 4));
@@ -561,13 +587,26 @@ class HipExecutor : public Executor {
     g.bias = b_p_; g.C = X_; g.ldc = D; g.N = D;
     g.rowinfo = rowinfo_; g.pe = pe_; g.c_ref = c_ref_; g.c_other = c_other_;
     HIPCHECK(run_gemm(EPI_PATCH, g));
+    // fp8: activations feeding the QKV and MLP GEMMs are quantised per window (dynamic scales)
+    const int nwin = (int)p.gsegs.size();
+    int max_rows = 0;
+    for (const AttnSeg& w : p.gsegs) max_rows = std::max(max_rows, w.nf * w.npad);
+    auto quant = [&](const void* y, int C, unsigned char* q, float* srow) {
+      return window_quant_fp8((const __bf16*)y, C, gsegs, nwin, max_rows, amax_, q, srow, st_);
+    };
     for (int l = 0; l < layers; ++l) {
       const LayerW& L = layers_[l];
       HIPCHECK(layernorm(dt_, X_, Y_, L.ln1_g, L.ln1_b, M, D, nullptr, st_));
       GemmArgs q{};
       q.A = Y_; q.lda = D; q.Bt = L.Wqkv; q.ldb = D; q.M = M; q.N = 3 * D; q.K = D; q.bias = L.b_qkv;
       q.q = Q_; q.k = K_; q.vt = Vt_; q.heads = H_; q.hd = hd_; q.mpad = mpad_;
-      HIPCHECK(run_gemm(EPI_QKV, q));
+      if (fp8_) {
+        HIPCHECK(quant(Y_, D, Y8_, srow_));
+        q.A = Y8_;
+        q.ascale = srow_;
+        q.bscale = wscale_ + 3 * l;
+      }
+      HIPCHECK(run_gemm(EPI_QKV, q, fp8_));
       const bool global = (l % 2) == 1;
       prof_begin();
       if (global)
@@ -582,11 +621,23 @@ class HipExecutor : public Executor {
       GemmArgs f1{};
       f1.A = Y_; f1.lda = D; f1.Bt = L.W1; f1.ldb = D; f1.M = M; f1.N = F_; f1.K = D; f1.bias = L.b_1;
       f1.C = Hb_; f1.ldc = F_;
-      HIPCHECK(run_gemm(EPI_GELU, f1));
+      if (fp8_) {
+        HIPCHECK(quant(Y_, D, Y8_, srow_));
+        f1.A = Y8_;
+        f1.ascale = srow_;
+        f1.bscale = wscale_ + 3 * l + 1;
+      }
+      HIPCHECK(run_gemm(EPI_GELU, f1, fp8_));
       GemmArgs f2{};
       f2.A = Hb_; f2.lda = F_; f2.Bt = L.W2; f2.ldb = F_; f2.M = M; f2.N = D; f2.K = F_; f2.bias = L.b_2;
       f2.C = X_; f2.ldc = D;
-      HIPCHECK(run_gemm(EPI_RESID, f2));
+      if (fp8_) {
+        HIPCHECK(quant(Hb_, F_, H8_, srow2_));
+        f2.A = H8_;
+        f2.ascale = srow2_;
+        f2.bscale = wscale_ + 3 * l + 2;
+      }
+      HIPCHECK(run_gemm(EPI_RESID, f2, fp8_));
     }
     if (layers == depth_) {
       const int Fr = (int)p.frames.size();
@@ -600,9 +651,9 @@ class HipExecutor : public Executor {
     return MF_OK;
   }
 
-  hipError_t run_gemm(Epi e, const GemmArgs& a) {
+  hipError_t run_gemm(Epi e, const GemmArgs& a, bool fp8 = false) {
     prof_begin();
-    const hipError_t r = gemm(dt_, e, a, st_);
+    const hipError_t r = gemm(fp8 ? DT_FP8 : dt_, e, a, st_);
     prof_end(3);
     return r;
   }
@@ -664,6 +715,7 @@ class HipExecutor : public Executor {
     F(wdev_); F(Wp_); F(H1t_);
     for (auto& L : layers_) { F(L.Wqkv); F(L.Wo); F(L.W1); F(L.W2); }
     F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(Q_); F(K_); F(Vt_);
+    F(Y8_); F(H8_); F(srow_); F(srow2_); F(amax_); F(wscale_); F(wamax_);
     F(camln_); F(camg_); F(pose9_); F(tloc_); F(res_); F(keys_); F(pe_); F(tab_dev_);
     if (res_host_) hipHostFree(res_host_);
     if (tab_host_) hipHostFree(tab_host_);
@@ -705,6 +757,10 @@ class HipExecutor : public Executor {
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   bool profiling_ = false;
   bool use_graphs_ = false;
+  bool fp8_ = false;
+  unsigned char *Y8_ = nullptr, *H8_ = nullptr;
+  float *srow_ = nullptr, *srow2_ = nullptr, *wscale_ = nullptr;
+  unsigned *amax_ = nullptr, *wamax_ = nullptr;
   struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     std::vector<ProfEv> prof;   // timing events recorded inside the graph (profiled shapes)

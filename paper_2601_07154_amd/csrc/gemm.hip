@@ -16,20 +16,35 @@
 
 namespace mf {
 
+// One MFMA over a lane's NCH 16-byte k-fragments of A and B.
 template <typename T> struct Mma;
 template <> struct Mma<bf16> {
-  static MF_DEV void run(const u32x4& a, const u32x4& b, f32x16& c) {
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&a, *(const bf16x8*)&b, c, 0, 0, 0);
+  static constexpr int NCH = 1;
+  static MF_DEV void run(const u32x4* a, const u32x4* b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)a, *(const bf16x8*)b, c, 0, 0, 0);
   }
 };
 template <> struct Mma<float> {
-  static MF_DEV void run(const u32x4& a, const u32x4& b, f32x16& c) {
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  static constexpr int NCH = 1;
+  static MF_DEV void run(const u32x4* a, const u32x4* b, f32x16& c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a->x), __uint_as_float(b->x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a->y), __uint_as_float(b->y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a->z), __uint_as_float(b->z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a->w), __uint_as_float(b->w), c, 0, 0, 0);
   }
 };
+// OCP E4M3 operands: v_mfma_scale_f32_32x32x64_f8f6f4 (format 0 = E4M3 for A and B), block scales
+// 127 (2^0: the per-tensor scales are applied in the epilogue); 32 bytes of k per lane.
+template <> struct Mma<fp8> {
+  static constexpr int NCH = 2;
+  static MF_DEV void run(const u32x4* a, const u32x4* b, f32x16& c) {
+    const i32x8 av = {(int)a[0].x, (int)a[0].y, (int)a[0].z, (int)a[0].w, (int)a[1].x, (int)a[1].y, (int)a[1].z, (int)a[1].w};
+    const i32x8 bv = {(int)b[0].x, (int)b[0].y, (int)b[0].z, (int)b[0].w, (int)b[1].x, (int)b[1].y, (int)b[1].z, (int)b[1].w};
+    c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
+  }
+};
+template <typename T> struct OutT { using type = T; };
+template <> struct OutT<fp8> { using type = bf16; };   // fp8 GEMMs write bf16 (or fp32 residuals)
 
 // Element epilogues of the GELU / STORE / PATCH kinds (RESID and QKV are vectorised in the kernel).
 template <typename T, int EPI>
@@ -125,19 +140,23 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 #pragma unroll
       for (int i = 0; i < BCH; ++i) rb[i] = *(const u32x4*)(bptr[i] + kn);
     }
+    constexpr int NCH = Mma<T>::NCH, KK = 4 / NCH;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      u32x4 fa[WM], fb[WN];
-      const int ch = 2 * kk + g;
+    for (int kk = 0; kk < KK; ++kk) {
+      u32x4 fa[WM][NCH], fb[WN][NCH];
 #pragma unroll
-      for (int i = 0; i < WM; ++i) {
-        const int row = wr * 32 * WM + i * 32 + l32;
-        fa[i] = sA[row * 8 + (ch ^ ((row >> 1) & 7))];
-      }
+      for (int q = 0; q < NCH; ++q) {
+        const int ch = NCH == 1 ? 2 * kk + g : 4 * kk + 2 * g + q;
 #pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        const int row = wc * 32 * WN + j * 32 + l32;
-        fb[j] = sB[row * 8 + (ch ^ ((row >> 1) & 7))];
+        for (int i = 0; i < WM; ++i) {
+          const int row = wr * 32 * WM + i * 32 + l32;
+          fa[i][q] = sA[row * 8 + (ch ^ ((row >> 1) & 7))];
+        }
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          const int row = wc * 32 * WN + j * 32 + l32;
+          fb[j][q] = sB[row * 8 + (ch ^ ((row >> 1) & 7))];
+        }
       }
 #pragma unroll
       for (int i = 0; i < WM; ++i)
@@ -152,13 +171,16 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 
   // The q / k / v block of a QKV tile is uniform (the block width D is a multiple of BN):
   // resolve it once per workgroup.
+  using To = typename OutT<T>::type;   // element type of the q/k/v, GELU and STORE outputs
+  // fp8 operands carry per-tensor scales: a per-row scale of A (its window's) and one of B
+  const float bs = a.ascale ? a.bscale[0] : 1.0f;
   int which = 0, nbase = 0;
-  T* dst = nullptr;
+  To* dst = nullptr;
   if constexpr (EPI == EPI_QKV) {
     const int D = a.heads * a.hd;
     which = a.qkv_which0 + n0 / D;
     nbase = (n0 / D) * D;
-    dst = (T*)(which == 0 ? a.q : (which == 1 ? a.k : a.vt));
+    dst = (To*)(which == 0 ? a.q : (which == 1 ? a.k : a.vt));
   }
   if constexpr (TC) {
     // lane (l32, g) of tile (i, j): row m, columns nb + 8 rg + e (rg, e < 4)
@@ -166,6 +188,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
     for (int i = 0; i < WM; ++i) {
       const int m = m0 + wr * 32 * WM + i * 32 + l32;
       if (m >= a.M) continue;
+      const float sc = a.ascale ? a.ascale[m] * bs : 1.0f;
       int32_t ri = 0;
       if constexpr (EPI == EPI_PATCH) ri = a.rowinfo[m];
 #pragma unroll
@@ -173,7 +196,8 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 #pragma unroll
         for (int rg = 0; rg < 4; ++rg) {
           const int n = n0 + wc * 32 * WN + j * 32 + 4 * g + 8 * rg;
-          f32x4 v = {acc[i][j][4 * rg], acc[i][j][4 * rg + 1], acc[i][j][4 * rg + 2], acc[i][j][4 * rg + 3]};
+          f32x4 v = {acc[i][j][4 * rg] * sc, acc[i][j][4 * rg + 1] * sc, acc[i][j][4 * rg + 2] * sc,
+                     acc[i][j][4 * rg + 3] * sc};
           if constexpr (EPI != EPI_PATCH) {
             if (a.bias) v += *(const f32x4*)(a.bias + n);
           }
@@ -192,17 +216,17 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
           } else {
             if constexpr (EPI == EPI_GELU) {
 #pragma unroll
-              for (int e = 0; e < 4; ++e) v[e] = sizeof(T) == 2 ? gelu_erf_fast(v[e]) : gelu_erf(v[e]);
+              for (int e = 0; e < 4; ++e) v[e] = sizeof(To) == 2 ? gelu_erf_fast(v[e]) : gelu_erf(v[e]);
             }
-            T* out;
+            To* out;
             if constexpr (EPI == EPI_QKV) {
               const int nn = n - nbase;
               const int h = nn / a.hd, d = nn - h * a.hd;
               out = dst + ((int64_t)h * a.mpad + m) * a.hd + d;
             } else {
-              out = (T*)a.C + (int64_t)m * a.ldc + n;
+              out = (To*)a.C + (int64_t)m * a.ldc + n;
             }
-            if constexpr (sizeof(T) == 2) {
+            if constexpr (sizeof(To) == 2) {
               bf16x4 b;
 #pragma unroll
               for (int e = 0; e < 4; ++e) b[e] = (bf16)v[e];
@@ -226,34 +250,37 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
           const int h = nn / a.hd, d = nn - h * a.hd;
           const float bn = a.bias[n];
           if (which < 2) {
-            T* col = dst + (int64_t)h * a.mpad * a.hd + d;
+            To* col = dst + (int64_t)h * a.mpad * a.hd + d;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int m = mb + 8 * (r >> 2) + (r & 3);
-              if (m < a.M) col[(int64_t)m * a.hd] = from_f32<T>(acc[i][j][r] + bn);
+              if (m < a.M) col[(int64_t)m * a.hd] = from_f32<To>(acc[i][j][r] * (a.ascale ? a.ascale[m] * bs : 1.0f) + bn);
             }
           } else {
             // V^T: the four rows of a register group are consecutive keys -> one vector store
-            T* row = dst + ((int64_t)h * a.hd + d) * a.mpad;
+            To* row = dst + ((int64_t)h * a.hd + d) * a.mpad;
 #pragma unroll
             for (int rg = 0; rg < 4; ++rg) {
               const int m = mb + 8 * rg;
+              float sc[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) sc[e] = a.ascale ? a.ascale[min(m + e, a.M - 1)] * bs : 1.0f;
               if (m + 3 < a.M) {
-                if constexpr (sizeof(T) == 2) {
+                if constexpr (sizeof(To) == 2) {
                   bf16x4 v;
 #pragma unroll
-                  for (int e = 0; e < 4; ++e) v[e] = (bf16)(acc[i][j][4 * rg + e] + bn);
+                  for (int e = 0; e < 4; ++e) v[e] = (bf16)(acc[i][j][4 * rg + e] * sc[e] + bn);
                   *(bf16x4*)(row + m) = v;
                 } else {
                   f32x4 v;
 #pragma unroll
-                  for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * rg + e] + bn;
+                  for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * rg + e] * sc[e] + bn;
                   *(f32x4*)(row + m) = v;
                 }
               } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                  if (m + e < a.M) row[m + e] = from_f32<T>(acc[i][j][4 * rg + e] + bn);
+                  if (m + e < a.M) row[m + e] = from_f32<To>(acc[i][j][4 * rg + e] * sc[e] + bn);
               }
             }
           }
@@ -261,7 +288,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const int m = mb + 8 * (r >> 2) + (r & 3);
-            if (m < a.M) epilogue<T, EPI>(a, m, n, acc[i][j][r]);
+            if (m < a.M) epilogue<To, EPI>(a, m, n, acc[i][j][r] * (a.ascale ? a.ascale[m] * bs : 1.0f));
           }
         }
       }
@@ -280,7 +307,7 @@ static hipError_t launch_tile(const GemmArgs& a, hipStream_t s) {
 template <typename T, int EPI, int TC>
 static hipError_t launch_shape(const GemmArgs& a, hipStream_t s) {
   // 256 x 128 tiles (waves of 128 x 64: fewer LDS bytes per MFMA) once there are enough of them
-  if (sizeof(T) == 2 && (int64_t)((a.M + 255) / 256) * (a.N / 128) >= 512) return launch_tile<T, EPI, 4, 2, TC>(a, s);
+  if (sizeof(T) <= 2 && (int64_t)((a.M + 255) / 256) * (a.N / 128) >= 512) return launch_tile<T, EPI, 4, 2, TC>(a, s);
   return launch_tile<T, EPI, 2, 2, TC>(a, s);
 }
 
@@ -322,6 +349,11 @@ static hipError_t dispatch(Epi epi, const GemmArgs& a, hipStream_t s) {
 }
 
 hipError_t gemm(Dtype dt, Epi epi, const GemmArgs& a, hipStream_t s) {
+  if (dt == DT_FP8) {
+    if (epi == EPI_PATCH || epi == EPI_STORE) return hipErrorInvalidValue;   // not used with fp8
+    if (!a.ascale || !a.bscale) return hipErrorInvalidValue;
+    return dispatch<fp8>(epi, a, s);
+  }
   return dt == DT_BF16 ? dispatch<bf16>(epi, a, s) : dispatch<float>(epi, a, s);
 }
 

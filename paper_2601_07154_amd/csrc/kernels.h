@@ -5,7 +5,7 @@
 
 namespace mf {
 
-enum Dtype { DT_F32 = 0, DT_BF16 = 1 };
+enum Dtype { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };   // DT_FP8: OCP E4M3 bytes
 
 // ---------------------------------------------------------------- GEMM  C = A Bt^T (+ epilogue)
 enum Epi { EPI_RESID = 1, EPI_GELU = 2, EPI_QKV = 3, EPI_PATCH = 4, EPI_STORE = 5 };
@@ -19,6 +19,8 @@ struct GemmArgs {
   // EPI_QKV: Q, K head-major [H][mpad][hd], V transposed [H][hd][mpad]
   void* q; void* k; void* vt; int heads; int hd; int64_t mpad;
   int qkv_which0;                  // block (0 q, 1 k, 2 v) of column 0 of this launch (set internally)
+  // fp8 operands: per-row scale of A [M] and the scale of B [1] (device); null otherwise
+  const float* ascale; const float* bscale;
   // EPI_PATCH: per-row kind/PE row (rowinfo), PE table [rows][N] fp32, camera tokens
   const int32_t* rowinfo; const float* pe; const float* c_ref; const float* c_other;
 };
@@ -55,6 +57,16 @@ hipError_t make_pe(float* pe, int gh, int gw, int dim, hipStream_t s);
 // out[c * ld_out + r] = w[r * cols + c]
 hipError_t convert_transpose(Dtype dt, const float* w, int rows, int cols, void* out, int ld_out,
                              hipStream_t s);
+
+// ---------------------------------------------------------------- FP8 (OCP E4M3) quantisation
+// Per-window dynamic scales: q = E4M3(y / s_w), s_w = amax over window w's valid rows / 448; srow[m] =
+// the scale of row m's window.  amax: [nwin] scratch (cleared here).  y [rows][C] bf16, C % 16 == 0.
+hipError_t window_quant_fp8(const __bf16* y, int C, const AttnSeg* wins, int nwin, int max_rows, unsigned* amax,
+                            unsigned char* q, float* srow, hipStream_t s);
+// Static per-tensor weight scale: out[c * ld + r] = E4M3(w[r][c] / s), s = amax(|w|) / 448 -> *scale.
+hipError_t quantize_weight_fp8(const float* w, int rows, int cols, unsigned char* out, int ld, unsigned* amax_tmp,
+                               float* scale, hipStream_t s);
+hipError_t quantize_plain_fp8(const float* x, int64_t n, float scale, unsigned char* q, hipStream_t s);
 
 // ---------------------------------------------------------------- pose head tail
 // g: [F, D] fp32 (after Linear-GELU), H2: [D, 9] fp32, h2: [9] -> pose9 [F, 9] fp32, T_loc [F,16] fp64

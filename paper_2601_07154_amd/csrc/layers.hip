@@ -198,3 +198,142 @@ hipError_t pose_out(const float* g, const float* H2, const float* h2, int F, int
 }
 
 }  // namespace mf
+
+// ------------------------------------------------------------------ FP8 (OCP E4M3) quantisation
+namespace mf {
+
+// fp32 -> E4M3 with round-to-nearest-even, saturating at +-448 (the scale maps the amax to 448).
+MF_DEV unsigned pack4_fp8(float a, float b, float c, float d) {
+  a = fminf(fmaxf(a, -448.0f), 448.0f);
+  b = fminf(fmaxf(b, -448.0f), 448.0f);
+  c = fminf(fmaxf(c, -448.0f), 448.0f);
+  d = fminf(fmaxf(d, -448.0f), 448.0f);
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  return (unsigned)w;
+}
+
+__global__ void fill_u32_kernel(unsigned* p, int n, unsigned v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Per-window amax of bf16 rows [rows][C] over the valid (non-padding) token rows of each window.
+// Block (x, w): rows base + 16 x .. +15 of window w; 16 threads per row.
+__global__ __launch_bounds__(256) void window_amax_kernel(const bf16* __restrict__ y, int C,
+                                                          const AttnSeg* __restrict__ wins,
+                                                          unsigned* __restrict__ amax) {
+  const AttnSeg w = wins[blockIdx.y];
+  const int rel = blockIdx.x * 16 + (threadIdx.x >> 4);
+  float mx = 0.0f;
+  if (rel < w.nf * w.npad && (rel % w.npad) < w.n) {
+    const bf16* row = y + (int64_t)(w.base + rel) * C;
+    for (int c = (threadIdx.x & 15) * 8; c < C; c += 128) {
+      const bf16x8 v = *(const bf16x8*)(row + c);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf((float)v[e]));
+    }
+  }
+  mx = wave_max(mx);
+  __shared__ float red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    atomicMax(&amax[blockIdx.y], __float_as_uint(m));   // non-negative floats order as unsigned
+  }
+}
+
+// q = E4M3(y / s), s = amax / 448 of the row's window (1 if the window is all zero); every row of
+// the window (padding rows included) gets srow = s.  Block (x, w): 16 rows, 16 threads per row,
+// each thread 16 consecutive columns per step (C a multiple of 16).
+__global__ __launch_bounds__(256) void window_quant_kernel(const bf16* __restrict__ y, int C,
+                                                           const AttnSeg* __restrict__ wins,
+                                                           const unsigned* __restrict__ amax,
+                                                           fp8* __restrict__ q, float* __restrict__ srow) {
+  const AttnSeg w = wins[blockIdx.y];
+  const int rel = blockIdx.x * 16 + (threadIdx.x >> 4);
+  if (rel >= w.nf * w.npad) return;
+  const float am = __uint_as_float(amax[blockIdx.y]);
+  const float s = am > 0.0f ? am / 448.0f : 1.0f;
+  const float inv = 1.0f / s;
+  const int64_t r = w.base + rel;
+  const bf16* row = y + r * C;
+  fp8* qrow = q + r * C;
+  for (int c = (threadIdx.x & 15) * 16; c < C; c += 256) {
+    const bf16x8 v0 = *(const bf16x8*)(row + c);
+    const bf16x8 v1 = *(const bf16x8*)(row + c + 8);
+    u32x4 o;
+    o.x = pack4_fp8((float)v0[0] * inv, (float)v0[1] * inv, (float)v0[2] * inv, (float)v0[3] * inv);
+    o.y = pack4_fp8((float)v0[4] * inv, (float)v0[5] * inv, (float)v0[6] * inv, (float)v0[7] * inv);
+    o.z = pack4_fp8((float)v1[0] * inv, (float)v1[1] * inv, (float)v1[2] * inv, (float)v1[3] * inv);
+    o.w = pack4_fp8((float)v1[4] * inv, (float)v1[5] * inv, (float)v1[6] * inv, (float)v1[7] * inv);
+    *(u32x4*)(qrow + c) = o;
+  }
+  if ((threadIdx.x & 15) == 0) srow[r] = s;
+}
+
+hipError_t window_quant_fp8(const bf16* y, int C, const AttnSeg* wins, int nwin, int max_rows, unsigned* amax,
+                            fp8* q, float* srow, hipStream_t s) {
+  if (nwin <= 0) return hipSuccess;
+  if (C % 16 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((nwin + 255) / 256), dim3(256), 0, s, amax, nwin, 0u);
+  const dim3 grid((unsigned)((max_rows + 15) / 16), (unsigned)nwin);
+  hipLaunchKernelGGL(window_amax_kernel, grid, dim3(256), 0, s, y, C, wins, amax);
+  hipLaunchKernelGGL(window_quant_kernel, grid, dim3(256), 0, s, y, C, wins, amax, q, srow);
+  return hipGetLastError();
+}
+
+// Weights: amax of an fp32 tensor, then E4M3(w / s) transposed to [cols][rows] (ld), s = amax/448.
+__global__ void amax_f32_kernel(const float* __restrict__ w, int64_t n, unsigned* __restrict__ out) {
+  float mx = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    mx = fmaxf(mx, fabsf(w[i]));
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(mx));
+}
+
+__global__ void quant_transpose_kernel(const float* __restrict__ w, int rows, int cols, fp8* __restrict__ out,
+                                       int ld, const unsigned* __restrict__ amax, float* __restrict__ scale) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // 4 consecutive rows per thread
+  const int64_t n4 = (int64_t)(rows / 4) * cols;
+  const float am = __uint_as_float(*amax);
+  const float s = am > 0.0f ? am / 448.0f : 1.0f;
+  if (idx == 0) *scale = s;
+  if (idx >= n4) return;
+  const int c = (int)(idx % cols), r = (int)(idx / cols) * 4;
+  const float inv = 1.0f / s;
+  const unsigned p = pack4_fp8(w[(int64_t)r * cols + c] * inv, w[(int64_t)(r + 1) * cols + c] * inv,
+                               w[(int64_t)(r + 2) * cols + c] * inv, w[(int64_t)(r + 3) * cols + c] * inv);
+  *(unsigned*)(out + (int64_t)c * ld + r) = p;
+}
+
+hipError_t quantize_weight_fp8(const float* w, int rows, int cols, fp8* out, int ld, unsigned* amax_tmp,
+                               float* scale, hipStream_t s) {
+  if (rows % 4 != 0 || ld % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, amax_tmp, 1, 0u);
+  hipLaunchKernelGGL(amax_f32_kernel, dim3(1024), dim3(256), 0, s, w, (int64_t)rows * cols, amax_tmp);
+  const int64_t n4 = (int64_t)(rows / 4) * cols;
+  hipLaunchKernelGGL(quant_transpose_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, w, rows, cols, out,
+                     ld, amax_tmp, scale);
+  return hipGetLastError();
+}
+
+// Op-level: q[i] = E4M3(x[i] / scale) for fp32 x (n a multiple of 4).
+__global__ void quant_plain_kernel(const float* __restrict__ x, int64_t n4, float inv, unsigned* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  const f32x4 v = *(const f32x4*)(x + 4 * i);
+  q[i] = pack4_fp8(v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv);
+}
+
+hipError_t quantize_plain_fp8(const float* x, int64_t n, float scale, fp8* q, hipStream_t s) {
+  if (n % 4 != 0 || !(scale > 0.0f)) return hipErrorInvalidValue;
+  const int64_t n4 = n / 4;
+  if (n4 == 0) return hipSuccess;
+  hipLaunchKernelGGL(quant_plain_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, x, n4, 1.0f / scale,
+                     (unsigned*)q);
+  return hipGetLastError();
+}
+
+}  // namespace mf

@@ -1,6 +1,7 @@
 // Single-stage entry points (attention, GEMM, LayerNorm) over caller-provided device buffers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,49 @@ mf_status mf_op_gemm(int32_t precision, const void* A, const void* Bt, const flo
     r = gemm(DT_F32, EPI_STORE, a, (hipStream_t)stream);
   }
   if (r == hipSuccess) r = hipStreamSynchronize((hipStream_t)stream);
+  return r == hipSuccess ? MF_OK : MF_EDEVICE;
+}
+
+mf_status mf_op_gemm_fp8(const void* A, const void* Bt, const float* ascale, const float* bscale, const float* bias,
+                         float* C, int32_t M, int32_t N, int32_t K, void* stream) {
+  if (!A || !Bt || !C || !ascale || !bscale || M < 0 || N % 128 || K <= 0 || K % 128) return MF_EINVAL;
+  GemmArgs a{};
+  a.A = A; a.lda = K; a.Bt = Bt; a.ldb = K; a.M = M; a.N = N; a.K = K; a.bias = bias; a.C = C; a.ldc = N;
+  a.ascale = ascale; a.bscale = bscale;
+  hipError_t r = hipMemsetAsync(C, 0, (size_t)M * N * 4, (hipStream_t)stream);
+  if (r == hipSuccess) r = gemm(DT_FP8, EPI_RESID, a, (hipStream_t)stream);
+  if (r == hipSuccess) r = hipStreamSynchronize((hipStream_t)stream);
+  return r == hipSuccess ? MF_OK : MF_EDEVICE;
+}
+
+mf_status mf_op_quantize_fp8(const float* x, int64_t n, float scale, void* q, void* stream) {
+  if (!x || !q || n < 0 || n % 4 || !(scale > 0.0f)) return MF_EINVAL;
+  hipError_t r = quantize_plain_fp8(x, n, scale, (unsigned char*)q, (hipStream_t)stream);
+  if (r == hipSuccess) r = hipStreamSynchronize((hipStream_t)stream);
+  return r == hipSuccess ? MF_OK : MF_EDEVICE;
+}
+
+mf_status mf_op_quantize_fp8_windows(const void* y, int32_t C, const int32_t* segs, int32_t nwin, void* q,
+                                     float* srow, void* stream) {
+  if (!y || !q || !srow || !segs || nwin < 1 || C <= 0 || C % 16) return MF_EINVAL;
+  std::vector<AttnSeg> sg(nwin);
+  int max_rows = 0;
+  for (int i = 0; i < nwin; ++i) {
+    sg[i] = {segs[4 * i], segs[4 * i + 1], segs[4 * i + 2], segs[4 * i + 3]};
+    const AttnSeg& s = sg[i];
+    if (s.base < 0 || s.nf < 1 || s.n < 1 || s.npad < s.n) return MF_EINVAL;
+    max_rows = std::max(max_rows, s.nf * s.npad);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  void* dev = nullptr;
+  const size_t sb = sg.size() * sizeof(AttnSeg);
+  if (hipMalloc(&dev, sb + (size_t)nwin * 4) != hipSuccess) return MF_EDEVICE;
+  hipError_t r = hipMemcpyAsync(dev, sg.data(), sb, hipMemcpyHostToDevice, st);
+  if (r == hipSuccess)
+    r = window_quant_fp8((const __bf16*)y, C, (const AttnSeg*)dev, nwin, max_rows, (unsigned*)((char*)dev + sb),
+                         (unsigned char*)q, srow, st);
+  hipStreamSynchronize(st);
+  hipFree(dev);
   return r == hipSuccess ? MF_OK : MF_EDEVICE;
 }
 

@@ -96,9 +96,11 @@ def test_small_bf16_windows01(oracle_w01):
             assert abs(mp[r["peak_y"], r["peak_x"]] - 1.0) < 1e-6 and mp.max() <= 1.0 + 1e-6 and mp.min() >= 0.0
 
 
-def test_stream_alone_equals_stream_in_mix():
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_stream_alone_equals_stream_in_mix(precision):
     """Continuous batching does not change a stream's results: rows and segments are computed
-    independently of what else shares the batch, so the outputs are bitwise equal."""
+    independently of what else shares the batch (fp8 activation scales are per window), so the
+    outputs are bitwise equal."""
     torch = torch_cuda()
     m = mf()
     model = mf_synth.ModelConfig(4, 384, 6, 1536)
@@ -107,7 +109,7 @@ def test_stream_alone_equals_stream_in_mix():
     frames = [torch.from_numpy(mf_synth.make_frames(n, H, W, 40 + i)).cuda() for i, (H, W, L, O, n) in enumerate(geo)]
 
     def run(which):
-        eng = m.Engine.from_model(model, blob, precision="bf16", max_tokens=65536)
+        eng = m.Engine.from_model(model, blob, precision=precision, max_tokens=65536)
         sids = {}
         for i in which:
             H, W, L, O, n = geo[i]

@@ -226,3 +226,84 @@ def test_bf16_rounding_emulation():
     assert r[2] == 1.0 + 2 ** -6                                # tie to even (odd lower neighbour)
     assert r[3] == -3.140625
     assert torch.tensor(x).to(torch.bfloat16).double().numpy().tolist() == r.tolist()
+
+
+def e4m3_table():
+    """All finite OCP E4M3 values, decoded from the bit fields of the 8-bit codes:
+    sign s, exponent e (4 bits, bias 7), mantissa m (3 bits); e = 0 is subnormal
+    (m/8 * 2^-6); S.1111.111 is NaN (the only non-finite code)."""
+    vals = {}
+    for code in range(256):
+        s, e, m = code >> 7, (code >> 3) & 15, code & 7
+        if e == 15 and m == 7:
+            continue
+        mag = (m / 8.0) * 2.0 ** -6 if e == 0 else (1.0 + m / 8.0) * 2.0 ** (e - 7)
+        vals[code] = -mag if s else mag
+    return vals
+
+
+def test_e4m3_table_facts():
+    t = e4m3_table()
+    assert len(t) == 254
+    pos = sorted({v for v in t.values() if v >= 0})
+    assert pos[-1] == 448.0 == vit.E4M3_MAX
+    assert pos[1] == 2.0 ** -9                      # smallest subnormal
+    assert min(v for v in pos if v >= 2.0 ** -6) == vit.E4M3_MIN_NORMAL
+
+
+def test_round_e4m3_representables_and_ties():
+    """Brute force over the decoded code table: every finite value rounds to itself; every
+    midpoint between neighbours rounds to the neighbour with the even mantissa code; points
+    just off the midpoint go to the nearer neighbour; beyond 448 saturates."""
+    t = e4m3_table()
+    vals = np.array(sorted(set(t.values())))
+    assert np.array_equal(vit.round_e4m3(vals), vals)
+    pos = sorted((v, c) for c, v in t.items() if v > 0 or (v == 0 and c == 0))
+    for (lo, clo), (hi, chi) in zip(pos[:-1], pos[1:]):
+        mid = 0.5 * (lo + hi)
+        even = lo if (clo & 1) == 0 else hi
+        assert (chi & 1) != (clo & 1)
+        assert vit.round_e4m3(np.array([mid]))[0] == even
+        assert vit.round_e4m3(np.array([-mid]))[0] == -even
+        eps = (hi - lo) * 1e-6
+        assert vit.round_e4m3(np.array([mid - eps]))[0] == lo
+        assert vit.round_e4m3(np.array([mid + eps]))[0] == hi
+    assert vit.round_e4m3(np.array([449.0, 1e6, -500.0])).tolist() == [448.0, 448.0, -448.0]
+    assert vit.round_e4m3(np.array([2.0 ** -11]))[0] == 0.0      # below half the smallest subnormal
+
+
+def test_round_e4m3_is_nearest():
+    """For random inputs within range, no table value is strictly nearer than the result."""
+    vals = np.array(sorted(set(e4m3_table().values())))
+    x = RNG.standard_normal(2000) * np.exp(RNG.uniform(-8, 6, 2000))
+    x = x[np.abs(x) <= 448.0]
+    r = vit.round_e4m3(x)
+    best = np.min(np.abs(x[:, None] - vals[None, :]), axis=1)
+    assert np.all(np.isin(r, vals))
+    assert np.allclose(np.abs(x - r), best, rtol=0, atol=0)
+
+
+def test_quantise_e4m3_scale():
+    x = RNG.standard_normal((17, 33)) * 3.0
+    q, s = vit.quantise_e4m3(x)
+    assert s == np.max(np.abs(x)) / 448.0
+    assert np.max(np.abs(q)) == 448.0
+    assert np.max(np.abs(q * s - x) / np.maximum(np.abs(x), 2.0 ** -6 * s)) <= 2.0 ** -4 + 1e-12
+    assert vit.quantise_e4m3(np.zeros((3, 3)))[1] == 1.0
+
+
+def test_fp8_mode_only_changes_qkv_and_mlp():
+    """In fp8 mode matmul_q differs from the bf16 product by at most the E4M3 rounding of both
+    operands (relative 2^-4 each), and the plain matmul is unchanged."""
+    a = RNG.standard_normal((40, 64))
+    b = RNG.standard_normal((64, 48)) * 0.02
+    p8, pb = vit.Prec("fp8"), vit.Prec("bf16")
+    assert np.array_equal(p8.matmul(a, b), pb.matmul(a, b))
+    ref = a @ b
+    sa, sb = np.max(np.abs(a)) / 448.0, np.max(np.abs(b)) / 448.0
+    sub = 2.0 ** -10                                 # half the subnormal spacing, in units of the scale
+    bound = ((2 * 2.0 ** -4 + 2.0 ** -8) * (np.abs(a) @ np.abs(b))
+             + sub * sa * 1.1 * np.abs(b).sum(0)[None, :] + sub * sb * 1.1 * np.abs(a).sum(1)[:, None]
+             + sub * sub * sa * sb * a.shape[1] + 1e-12)
+    assert np.all(np.abs(p8.matmul_q(a, b) - ref) <= bound)
+    assert not np.array_equal(p8.matmul_q(a, b), pb.matmul(a, b))
