@@ -24,25 +24,32 @@ import mf_synth  # noqa: E402
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 
 
+def window_sizes(n_frames: int, window: int, overlap: int) -> list:
+    """Frames per window of one stream: windows start every window - overlap frames, plus a tail
+    window ending at the last frame when the stride does not land there (Sec. 2.2's sliding window)."""
+    if n_frames <= window:
+        return [n_frames] if n_frames > 0 else []
+    starts = list(range(0, n_frames - window + 1, window - overlap))
+    if starts[-1] + window < n_frames:
+        starts.append(n_frames - window)
+    return [window] * len(starts)
+
+
 def global_attention_flops(wl) -> float:
     """Algorithmic flops of one global-attention launch: every window of the stream, 4 T^2 D each
     (QK^T and PV, 2 flops per multiply-add), T = frames per window x tokens per frame."""
-    from oracle import motion  # schedule only (no arithmetic of the path)
-    sched = motion.window_schedule(wl.frames, wl.window, wl.overlap)
     n = wl.tokens_per_frame
-    return sum(4.0 * (w["size"] * n) ** 2 * wl.model.dim for w in sched)
+    return sum(4.0 * (S * n) ** 2 * wl.model.dim for S in window_sizes(wl.frames, wl.window, wl.overlap))
 
 
 def path_flops(wl) -> float:
-    from oracle import motion
-    sched = motion.window_schedule(wl.frames, wl.window, wl.overlap)
     n, D, F, L = wl.tokens_per_frame, wl.model.dim, wl.model.mlp, wl.model.depth
     tot = 0.0
-    for w in sched:
-        T = w["size"] * n
+    for S in window_sizes(wl.frames, wl.window, wl.overlap):
+        T = S * n
         gemm = 2.0 * T * D * (3 * D + D + 2 * F)
         tot += L * gemm + (L // 2) * 4.0 * T * T * D + (L - L // 2) * 4.0 * T * n * D
-        tot += 2.0 * w["size"] * (wl.height // 14) * (wl.width // 14) * 588 * D
+        tot += 2.0 * S * (wl.height // 14) * (wl.width // 14) * 588 * D
     return tot
 
 
@@ -52,8 +59,7 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, sigma: float, profile: 
     blob = mf_synth.make_weights(wl.model, wl.seed_weights)
     frames = torch.from_numpy(mf_synth.workload_frames(wl)).cuda()
     rows = mfp.rows_per_frame(wl.height, wl.width)
-    sched_frames = sum(w["size"] for w in __import__("oracle").motion.window_schedule(wl.frames, wl.window,
-                                                                                        wl.overlap))
+    sched_frames = sum(window_sizes(wl.frames, wl.window, wl.overlap))
     eng = mfp.Engine.from_model(wl.model, blob, precision=precision, max_tokens=sched_frames * rows + 64,
                                 graphs=graphs)
     K = (wl.fx, wl.fy, wl.cx, wl.cy)
@@ -100,7 +106,7 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, sigma: float, profile: 
 def cpu_baseline(wl, sigma: float):
     """The FP64 oracle on a bounded sample: window 0 (16 frames, all layers) plus chaining, focus
     and maps of its frames; frames/s extrapolated to the whole stream (7 windows per 64 frames)."""
-    from oracle import motion, pipeline, vit
+    from oracle import pipeline, vit
     blob = mf_synth.make_weights(wl.model, wl.seed_weights)
     w = vit.unpack_weights(blob, wl.model.depth, wl.model.dim, wl.model.mlp)
     frames = mf_synth.workload_frames(wl, wl.window)
@@ -108,7 +114,7 @@ def cpu_baseline(wl, sigma: float):
     out = pipeline.run_stream(frames, w, wl.model.heads, wl.window, wl.overlap, (wl.fx, wl.fy, wl.cx, wl.cy),
                               sigma=sigma)
     dt = time.perf_counter() - t0
-    nwin = len(motion.window_schedule(wl.frames, wl.window, wl.overlap))
+    nwin = len(window_sizes(wl.frames, wl.window, wl.overlap))
     fps = wl.frames / (nwin * dt)
     return fps, dt, out
 
@@ -173,6 +179,7 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--sigma", type=float, default=1000.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (an elementwise torch kernel) so that HBM counters "
@@ -208,7 +215,8 @@ def main():
         "dtype": args.precision, "data": "synthetic (seeded uniform pixels, seeded N(0,0.02) random-init weights)",
         "config": {"workload": wl.name, "frames": wl.frames, "height": wl.height, "width": wl.width,
                    "window": wl.window, "overlap": wl.overlap, "layers": wl.model.depth, "dim": wl.model.dim,
-                   "heads": wl.model.heads, "mlp": wl.model.mlp, "windows_per_step": 7,
+                   "heads": wl.model.heads, "mlp": wl.model.mlp,
+                   "windows_per_step": len(window_sizes(wl.frames, wl.window, wl.overlap)),
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(r["lat"], 50)), "p99": float(np.percentile(r["lat"], 99))},
         "path_tflops": path_flops(wl) * args.steps / r["seconds"] / 1e12,
@@ -231,6 +239,11 @@ def main():
         f = run_gpu(wl, "fp32", 2, 1, args.sigma)
         res["fp32_value"] = f["frames"] / f["seconds"]
         res["speedup_vs_fp32"] = fps / res["fp32_value"]
+    f8 = None
+    if not args.no_fp8 and args.precision == "bf16":
+        f8 = run_gpu(wl, "fp8", args.steps, args.warmup, args.sigma, profile=False, graphs=True)
+        res["fp8_value"] = f8["frames"] / f8["seconds"]
+        res["speedup_fp8_vs_bf16_graphs"] = res["fp8_value"] / res["value_graphs_unprofiled"]
     if not args.no_cpu_baseline:
         cfps, cdt, out = cpu_baseline(wl, args.sigma)
         res["cpu_baseline"] = {"value": cfps, "unit": "frames/s", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
@@ -244,6 +257,10 @@ def main():
         Tr = out["T_w"][:wl.window]
         res["pose_error_window0"] = {"rot_deg_max": float(rot_err_deg(Tg[:, :3, :3], Tr[:, :3, :3]).max()),
                                      "tdir_deg_max": float(dir_err_deg(Tg[:, :3, 3], Tr[:, :3, 3]).max())}
+        if f8 is not None:
+            T8 = f8["first"]["T_w2c"].reshape(-1, 4, 4)[:wl.window]
+            res["pose_error_window0_fp8"] = {"rot_deg_max": float(rot_err_deg(T8[:, :3, :3], Tr[:, :3, :3]).max()),
+                                             "tdir_deg_max": float(dir_err_deg(T8[:, :3, 3], Tr[:, :3, 3]).max())}
     print(json.dumps(res))
 
 
