@@ -46,29 +46,6 @@ template <> struct Mma<fp8> {
 template <typename T> struct OutT { using type = T; };
 template <> struct OutT<fp8> { using type = bf16; };   // fp8 GEMMs write bf16 (or fp32 residuals)
 
-// Element epilogues of the GELU / STORE / PATCH kinds (RESID and QKV are vectorised in the kernel).
-template <typename T, int EPI>
-MF_DEV void epilogue(const GemmArgs& a, int m, int n, float v) {
-  if (a.bias && EPI != EPI_PATCH) v += a.bias[n];
-  if constexpr (EPI == EPI_GELU) {
-    // bf16 outputs take the 1.5e-7-accurate rational erf; fp32 outputs the library erff
-    if constexpr (sizeof(T) == 2) ((T*)a.C)[(int64_t)m * a.ldc + n] = from_f32<T>(gelu_erf_fast(v));
-    else ((T*)a.C)[(int64_t)m * a.ldc + n] = from_f32<T>(gelu_erf(v));
-  } else if constexpr (EPI == EPI_STORE) {
-    ((T*)a.C)[(int64_t)m * a.ldc + n] = from_f32<T>(v);
-  } else if constexpr (EPI == EPI_PATCH) {
-    // rowinfo: bits 30-31 kind (0 patch, 1 reference camera, 2 other camera, 3 gap), low bits PE row
-    const int32_t ri = a.rowinfo[m];
-    const int kind = (ri >> 30) & 3;
-    float out;
-    if (kind == 0) out = v + a.bias[n] + a.pe[(int64_t)(ri & 0x3fffffff) * a.N + n];
-    else if (kind == 1) out = a.c_ref[n];
-    else if (kind == 2) out = a.c_other[n];
-    else out = 0.0f;
-    ((float*)a.C)[(int64_t)m * a.ldc + n] = out;
-  }
-}
-
 // TC = 1 computes each 32x32 tile transposed (the weight fragment as the MFMA's A operand), so
 // that a lane holds one output row and 4 consecutive columns per register group: every
 // epilogue access is a 16-byte (fp32) or 8-byte (bf16) vector.  TC = 0 (lane = one column, 4
@@ -80,8 +57,11 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   constexpr int BK = 8 * EPC;           // elements per 128-byte row slice
   constexpr int ACH = BM * 8 / 256, BCH = BN * 8 / 256;   // chunks per thread
   // one LDS stage: the next k-slice is prefetched into registers while this one is consumed
-  __shared__ u32x4 sA[BM * 8];
-  __shared__ u32x4 sB[BN * 8];
+  // main loop: A and B k-slices; epilogue: per-wave staging (4 x 64 x 36 floats at most)
+  constexpr int SMEM = (BM + BN) * 8 > 2304 ? (BM + BN) * 8 : 2304;
+  __shared__ u32x4 smem[SMEM];
+  u32x4* const sA = smem;
+  u32x4* const sB = smem + BM * 8;
 
   const int tilesN = a.N / BN;
   const int tilesM = (a.M + BM - 1) / BM;
@@ -140,6 +120,9 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 #pragma unroll
       for (int i = 0; i < BCH; ++i) rb[i] = *(const u32x4*)(bptr[i] + kn);
     }
+    // keep the prefetch ahead of the MFMAs: without this fence the scheduler sinks the loads to
+    // the end of the iteration, right before the wait that consumes them
+    __builtin_amdgcn_sched_barrier(0);
     constexpr int NCH = Mma<T>::NCH, KK = 4 / NCH;
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
@@ -169,6 +152,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
     __syncthreads();
   }
 
+  // ------------------------------------------------------------------------------ epilogue
   // The q / k / v block of a QKV tile is uniform (the block width D is a multiple of BN):
   // resolve it once per workgroup.
   using To = typename OutT<T>::type;   // element type of the q/k/v, GELU and STORE outputs
@@ -182,116 +166,137 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
     nbase = (n0 / D) * D;
     dst = (To*)(which == 0 ? a.q : (which == 1 ? a.k : a.vt));
   }
-  if constexpr (TC) {
-    // lane (l32, g) of tile (i, j): row m, columns nb + 8 rg + e (rg, e < 4)
+  static_assert(WN == 2, "the staged epilogue assumes 64 columns per wave");
+  if constexpr (EPI == EPI_PATCH) {
+    // once per batch: direct stores. rowinfo bits 30-31: 0 patch, 1 reference camera, 2 other
+    // camera, 3 padding; low bits the position-code row
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
       const int m = m0 + wr * 32 * WM + i * 32 + l32;
       if (m >= a.M) continue;
-      const float sc = a.ascale ? a.ascale[m] * bs : 1.0f;
-      int32_t ri = 0;
-      if constexpr (EPI == EPI_PATCH) ri = a.rowinfo[m];
+      const int32_t ri = a.rowinfo[m];
+      const int kind = (ri >> 30) & 3;
 #pragma unroll
       for (int j = 0; j < WN; ++j)
 #pragma unroll
         for (int rg = 0; rg < 4; ++rg) {
           const int n = n0 + wc * 32 * WN + j * 32 + 4 * g + 8 * rg;
-          f32x4 v = {acc[i][j][4 * rg] * sc, acc[i][j][4 * rg + 1] * sc, acc[i][j][4 * rg + 2] * sc,
-                     acc[i][j][4 * rg + 3] * sc};
-          if constexpr (EPI != EPI_PATCH) {
-            if (a.bias) v += *(const f32x4*)(a.bias + n);
-          }
+          const f32x4 v = {acc[i][j][4 * rg], acc[i][j][4 * rg + 1], acc[i][j][4 * rg + 2], acc[i][j][4 * rg + 3]};
+          f32x4 o;
+          if (kind == 0) o = v + *(const f32x4*)(a.bias + n) + *(const f32x4*)(a.pe + (int64_t)(ri & 0x3fffffff) * a.N + n);
+          else if (kind == 1) o = *(const f32x4*)(a.c_ref + n);
+          else if (kind == 2) o = *(const f32x4*)(a.c_other + n);
+          else o = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+          *(f32x4*)((float*)a.C + (int64_t)m * a.ldc + n) = o;
+        }
+    }
+  } else if constexpr (TC) {
+    // Row-major outputs.  A lane's accumulators hold one row and 4-column groups; written as they
+    // are, a wave store would touch 32 rows with 16 bytes each.  Each wave's 32 x 64 block of a
+    // chunk i is staged through LDS instead and read back so that 16 lanes cover one row's 64
+    // consecutive columns: every global access is a row-contiguous run of 128 B (bf16) or 256 B.
+    constexpr int SR = 68;   // floats per staged row: 16-byte aligned, rows 4 banks apart
+    float* stage = (float*)smem + wave * (32 * SR);
+    const int rr = lane >> 4, c4 = (lane & 15) * 4;
+    const int nb = n0 + wc * 64 + c4;
+    f32x4 bias4 = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (a.bias) bias4 = *(const f32x4*)(a.bias + nb);
+    int64_t qoff = 0;   // QKV: head-major offset of column nb (4 columns stay within one head)
+    if constexpr (EPI == EPI_QKV) {
+      const int nn = nb - nbase;
+      const int h = nn / a.hd, d = nn - h * a.hd;
+      qoff = (int64_t)h * a.mpad * a.hd + d;
+    }
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg)
+          *(f32x4*)(stage + l32 * SR + j * 32 + 8 * rg + 4 * g) =
+              (f32x4){acc[i][j][4 * rg], acc[i][j][4 * rg + 1], acc[i][j][4 * rg + 2], acc[i][j][4 * rg + 3]};
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int r = rr + 4 * p;
+        const int m = m0 + wr * 32 * WM + i * 32 + r;
+        if (m < a.M) {
+          f32x4 v = *(const f32x4*)(stage + r * SR + c4);
+          const float sc = a.ascale ? a.ascale[m] * bs : 1.0f;
+          v = v * sc + bias4;
           if constexpr (EPI == EPI_RESID) {
-            f32x4* c = (f32x4*)((float*)a.C + (int64_t)m * a.ldc + n);
+            f32x4* c = (f32x4*)((float*)a.C + (int64_t)m * a.ldc + nb);
             *c = *c + v;
-          } else if constexpr (EPI == EPI_PATCH) {
-            // rowinfo bits 30-31: 0 patch, 1 reference camera, 2 other camera, 3 padding
-            const int kind = (ri >> 30) & 3;
-            f32x4 o;
-            if (kind == 0) o = v + *(const f32x4*)(a.bias + n) + *(const f32x4*)(a.pe + (int64_t)(ri & 0x3fffffff) * a.N + n);
-            else if (kind == 1) o = *(const f32x4*)(a.c_ref + n);
-            else if (kind == 2) o = *(const f32x4*)(a.c_other + n);
-            else o = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-            *(f32x4*)((float*)a.C + (int64_t)m * a.ldc + n) = o;
           } else {
             if constexpr (EPI == EPI_GELU) {
 #pragma unroll
               for (int e = 0; e < 4; ++e) v[e] = sizeof(To) == 2 ? gelu_erf_fast(v[e]) : gelu_erf(v[e]);
             }
             To* out;
-            if constexpr (EPI == EPI_QKV) {
-              const int nn = n - nbase;
-              const int h = nn / a.hd, d = nn - h * a.hd;
-              out = dst + ((int64_t)h * a.mpad + m) * a.hd + d;
-            } else {
-              out = (To*)a.C + (int64_t)m * a.ldc + n;
-            }
+            if constexpr (EPI == EPI_QKV) out = dst + qoff + (int64_t)m * a.hd;
+            else out = (To*)a.C + (int64_t)m * a.ldc + nb;
             if constexpr (sizeof(To) == 2) {
-              bf16x4 b;
+              bf16x4 o;
 #pragma unroll
-              for (int e = 0; e < 4; ++e) b[e] = (bf16)v[e];
-              *(bf16x4*)out = b;
+              for (int e = 0; e < 4; ++e) o[e] = (bf16)v[e];
+              *(bf16x4*)out = o;
             } else {
               *(f32x4*)out = v;
             }
           }
         }
+      }
     }
   } else {
-    // lane (l32, g) of tile (i, j): column n, rows mb + 8 rg + e
+    // V^T of the QKV projection (lane = column, 4 consecutive rows per register group): staged
+    // transposed, [column][row], so that 8 lanes read one column's 32 consecutive rows = keys.
+    static_assert(EPI == EPI_QKV, "untransposed tiles are used for the V^T store only");
+    constexpr int SV = 36;   // floats per staged column: 16-byte aligned, 4-bank-group spread
+    float* stage = (float*)smem + wave * (64 * SV);
+    const int cc = lane >> 3, r4 = (lane & 7) * 4;
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i) {
+      __syncthreads();
 #pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        const int n = n0 + wc * 32 * WN + j * 32 + l32;
-        const int mb = m0 + wr * 32 * WM + i * 32 + 4 * g;
-        if constexpr (EPI == EPI_QKV) {
-          const int nn = n - nbase;
-          const int h = nn / a.hd, d = nn - h * a.hd;
-          const float bn = a.bias[n];
-          if (which < 2) {
-            To* col = dst + (int64_t)h * a.mpad * a.hd + d;
+      for (int j = 0; j < WN; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int m = mb + 8 * (r >> 2) + (r & 3);
-              if (m < a.M) col[(int64_t)m * a.hd] = from_f32<To>(acc[i][j][r] * (a.ascale ? a.ascale[m] * bs : 1.0f) + bn);
-            }
+        for (int rg = 0; rg < 4; ++rg)
+          *(f32x4*)(stage + (j * 32 + l32) * SV + 8 * rg + 4 * g) =
+              (f32x4){acc[i][j][4 * rg], acc[i][j][4 * rg + 1], acc[i][j][4 * rg + 2], acc[i][j][4 * rg + 3]};
+      __syncthreads();
+      const int mb = m0 + wr * 32 * WM + i * 32 + r4;
+      float sc[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sc[e] = a.ascale ? a.ascale[min(mb + e, a.M - 1)] * bs : 1.0f;
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int c = cc + 8 * p;
+        const int n = n0 + wc * 64 + c;
+        const int nn = n - nbase;
+        const int h = nn / a.hd, d = nn - h * a.hd;
+        const float bn = a.bias[n];
+        const f32x4 v = *(const f32x4*)(stage + c * SV + r4);
+        To* row = dst + ((int64_t)h * a.hd + d) * a.mpad;
+        if (mb + 3 < a.M) {
+          if constexpr (sizeof(To) == 2) {
+            bf16x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (bf16)(v[e] * sc[e] + bn);
+            *(bf16x4*)(row + mb) = o;
           } else {
-            // V^T: the four rows of a register group are consecutive keys -> one vector store
-            To* row = dst + ((int64_t)h * a.hd + d) * a.mpad;
+            f32x4 o;
 #pragma unroll
-            for (int rg = 0; rg < 4; ++rg) {
-              const int m = mb + 8 * rg;
-              float sc[4];
-#pragma unroll
-              for (int e = 0; e < 4; ++e) sc[e] = a.ascale ? a.ascale[min(m + e, a.M - 1)] * bs : 1.0f;
-              if (m + 3 < a.M) {
-                if constexpr (sizeof(To) == 2) {
-                  bf16x4 v;
-#pragma unroll
-                  for (int e = 0; e < 4; ++e) v[e] = (bf16)(acc[i][j][4 * rg + e] * sc[e] + bn);
-                  *(bf16x4*)(row + m) = v;
-                } else {
-                  f32x4 v;
-#pragma unroll
-                  for (int e = 0; e < 4; ++e) v[e] = acc[i][j][4 * rg + e] * sc[e] + bn;
-                  *(f32x4*)(row + m) = v;
-                }
-              } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                  if (m + e < a.M) row[m + e] = from_f32<To>(acc[i][j][4 * rg + e] * sc[e] + bn);
-              }
-            }
+            for (int e = 0; e < 4; ++e) o[e] = v[e] * sc[e] + bn;
+            *(f32x4*)(row + mb) = o;
           }
         } else {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int m = mb + 8 * (r >> 2) + (r & 3);
-            if (m < a.M) epilogue<To, EPI>(a, m, n, acc[i][j][r] * (a.ascale ? a.ascale[m] * bs : 1.0f));
-          }
+          for (int e = 0; e < 4; ++e)
+            if (mb + e < a.M) row[mb + e] = from_f32<To>(v[e] * sc[e] + bn);
         }
       }
+    }
   }
 }
 
