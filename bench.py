@@ -227,7 +227,7 @@ def main():
     avg_ms = prof["attn_global_ms"] / calls
     flops = global_attention_flops(wl)
     ach = flops / (avg_ms * 1e-3) / 1e12
-    res["roofline"] = {"kernel": "global flash attention (attn_kernel<bf16,64>)", "bound": "mfma",
+    res["roofline"] = {"kernel": "global flash attention (attn_kernel_v3, bf16, hd 64)", "bound": "mfma",
                        "achieved": ach, "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
                        "frac": ach / PEAK_TFLOPS[args.precision], "traffic": None,
                        "avg_launch_ms": avg_ms, "launches": prof["attn_global_calls"],

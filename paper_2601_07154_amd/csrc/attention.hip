@@ -7,7 +7,7 @@
 // running-max rescaling of flash attention: scores never leave registers.
 //
 // attn_kernel (fp32, and bf16 with hd 32): each workgroup (4 waves) takes 128 queries of one
-// segment and one head; each wave owns 32 queries.  attn_kernel_v2 (bf16, hd 64) doubles the
+// segment and one head; each wave owns 32 queries.  attn_kernel_v3 (bf16, hd 64) doubles the
 // queries per wave (below).  Scores are computed transposed, S^T = K Q^T, so that each lane holds one query
 // column: the row max is a reduction over the lane's 16 values plus one exchange between
 // the two lane halves.  The probabilities feed O^T = V^T P^T directly from registers as the
@@ -265,43 +265,61 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
 }
 
 
-// ------------------------------------------------------------------ bf16, hd = 64, 64 queries/wave
+// ------------------------------------------------------------------ bf16, hd 64 (attn_kernel_v3)
 // Each wave owns two 32-query blocks that share every K and V^T fragment read from LDS (half
 // the LDS traffic per flop of one block per wave); a workgroup covers 256 queries.  Keys are
-// staged in LDS tiles of 128 (double-buffered, two barriers per tile) and consumed in 32-key
-// steps that are software-pipelined: the S^T MFMAs of step t+1 are issued before the softmax
-// of step t, so the matrix cores work while the vector ALUs exponentiate.  The running max is
-// only moved when a step's max exceeds it by more than 2^8 (the probabilities then stay <= 256,
-// exact in fp32 and representable in bf16), so the O rescale is rare.  Row sums are taken
-// from the bf16-rounded probabilities that the PV product uses (v_dot2), so numerator and
-// denominator see the same weights.  V^T tiles are stored with the keys of each 16-key group
-// reordered [0-3, 8-11, 4-7, 12-15] so that a lane's PV fragment is one 16-byte LDS read.
-namespace v2 {
+// staged in LDS tiles of 128 (double-buffered, one barrier per tile; the next tile passes
+// through 16 registers per thread, K during the first steps, V after) and consumed in 32-key
+// steps, unrolled four to a tile so every LDS offset is a constant.  Per step:
+//  - S^T = K Q^T with Q pre-scaled by log2(e)/sqrt(hd) once per workgroup, so the exp2 argument
+//    is s - m for the query's reference m;
+//  - m is set from the query's first-step maximum and raised only when a step's probabilities
+//    grow large (a lane's partial row sum above 2^12, which also catches an overflow to inf);
+//    no per-step maximum is computed otherwise, and the O rescale is rare;
+//  - the two query blocks finish one after the other (softmax, then PV), so the PV MFMAs of one
+//    block can overlap the softmax of the other;
+//  - row sums are taken from the bf16-rounded probabilities that the PV product uses (v_dot2),
+//    so numerator and denominator see the same weights.
+// V^T tiles are stored with the keys of each 16-key group reordered [0-3, 8-11, 4-7, 12-15] so
+// that a lane's PV fragment, in the key order of its probabilities, is one 16-byte LDS read.
+namespace v3 {
 constexpr int HD = 64, KT = 128, KS = 32, QW = 64, QT = 256;
 constexpr int KCPR = 8;    // 16-byte chunks per K row (64 d)
 constexpr int VCPR = 16;   // 16-byte chunks per V^T row (128 keys)
+constexpr float GROW = 4096.0f;
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 MF_DEV float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// S^T (32 keys x 32 queries) for both query blocks of the wave, keys `krow0`.. of LDS K tile.
-MF_DEV void qk_step(const u32x4* sKb, int krow0, int l32, int g, const u32x4 (&qf)[2][4], f32x16 (&s)[2]) {
-  const int krow = krow0 + l32;
-  u32x4 kf[4];
-#pragma unroll
-  for (int f = 0; f < 4; ++f) kf[f] = sKb[krow * KCPR + ((2 * f + g) ^ ((krow >> 1) & 7))];
-#pragma unroll
-  for (int hb = 0; hb < 2; ++hb) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) s[hb][r] = 0.0f;
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-      s[hb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf[f], *(const bf16x8*)&qf[hb][f], s[hb], 0, 0, 0);
-  }
+// v and the value of lane l ^ 32, combined (identically in both lanes)
+MF_DEV float pair_max(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+MF_DEV float pair_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-__global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict__ Q, const bf16* __restrict__ K,
+// p = exp2(s - m) as bf16 pairs (the B operand of PV, keys 4g.., 8+4g.. per 16-key half) and the
+// lane's partial row sum over those probabilities
+MF_DEV void probs(const f32x16& s, float m, u32x4 (&pf)[2], float& ls) {
+  const bf16x2_t ones = {(bf16)1.0f, (bf16)1.0f};
+  float acc = 0.0f;
+#pragma unroll
+  for (int j2 = 0; j2 < 2; ++j2)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x2 e = {fast_exp2(s[8 * j2 + 2 * q] - m), fast_exp2(s[8 * j2 + 2 * q + 1] - m)};
+      const bf16x2_t pr = __builtin_convertvector(e, bf16x2_t);
+      acc = __builtin_amdgcn_fdot2_f32_bf16(pr, ones, acc, false);
+      pf[j2][q] = __builtin_bit_cast(unsigned, pr);
+    }
+  ls = acc;
+}
+
+__global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict__ Q, const bf16* __restrict__ K,
                                                          const bf16* __restrict__ Vt, bf16* __restrict__ O,
                                                          int64_t mpad, int heads, int dim,
                                                          const AttnSeg* __restrict__ segs,
@@ -323,37 +341,48 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
   const bf16* Kh = K + ((int64_t)h * mpad + sg.base) * HD;
   const bf16* Vh = Vt + (int64_t)h * HD * mpad + sg.base;
 
+  // Q fragments, scaled to log2 units (one extra bf16 rounding of q * c)
   u32x4 qf[2][4];
 #pragma unroll
   for (int hb = 0; hb < 2; ++hb) {
     const u32x4* qr = (const u32x4*)(Qh + (int64_t)(qbase + hb * 32 + l32) * HD);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) qf[hb][f] = qr[2 * f + g];
+    for (int f = 0; f < 4; ++f) {
+      const u32x4 raw = qr[2 * f + g];
+      bf16x8 v = *(const bf16x8*)&raw;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (bf16)((float)v[e] * c);
+      qf[hb][f] = *(const u32x4*)&v;
+    }
   }
 
-  // K tile: thread -> chunks (row tid/8 + 32 i, col tid%8), i < 4.  V^T tile: thread -> row
-  // tid/4, keys 32 (tid%4) .. +31 (two 16-key groups), stored reordered (see above).
-  u32x4 rk[4], rv[4];
-  auto load_tile = [&](int kt) {
+  // K tile: thread -> row tid/2, chunks 4 (tid%2) .. +3.  V^T tile: thread -> row tid/4, keys
+  // 32 (tid%4) .. +31 (two 16-key groups), stored with keys 4-7 and 8-11 of every group swapped,
+  // the order of a lane's probabilities.
+  // The next tile is staged through 16 registers per thread, K first then V: the buffer it goes to
+  // was last read in the previous tile, which every wave has finished (one barrier per tile).
+  u32x4 rt[4];
+  auto load_k = [&](int kt) {
+    const u32x4* ksrc = (const u32x4*)(Kh + (int64_t)(kt + (tid >> 1)) * HD) + 4 * (tid & 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = (tid >> 3) + 32 * i, col = tid & 7;
-      rk[i] = *(const u32x4*)(Kh + (int64_t)(kt + row) * HD + col * 8);
-    }
+    for (int i = 0; i < 4; ++i) rt[i] = ksrc[i];
+  };
+  auto load_v = [&](int kt) {
     const u32x4* vsrc = (const u32x4*)(Vh + (int64_t)(tid >> 2) * mpad + kt + (tid & 3) * 32);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) rv[i] = vsrc[i];
+    for (int i = 0; i < 4; ++i) rt[i] = vsrc[i];
   };
-  auto store_tile = [&](int buf) {
+  auto store_k = [&](int buf) {
+    const int krow = tid >> 1, ksw = (krow >> 1) & 7;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = (tid >> 3) + 32 * i, col = tid & 7;
-      sK[buf][row * KCPR + (col ^ ((row >> 1) & 7))] = rk[i];
-    }
+    for (int i = 0; i < 4; ++i) sK[buf][krow * KCPR + ((4 * (tid & 1) + i) ^ ksw)] = rt[i];
+  };
+  auto store_v = [&](int buf) {
+    const u32x4* rv = rt;
     const int vrow = tid >> 2, sw = vrow & 15;
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const int ch = 4 * (tid & 3) + 2 * p;                         // first chunk of this 16-key group
+      const int ch = 4 * (tid & 3) + 2 * p;
       const u32x4 lo = {rv[2 * p].x, rv[2 * p].y, rv[2 * p + 1].x, rv[2 * p + 1].y};   // keys 0-3 | 8-11
       const u32x4 hi = {rv[2 * p].z, rv[2 * p].w, rv[2 * p + 1].z, rv[2 * p + 1].w};   // keys 4-7 | 12-15
       sV[buf][vrow * VCPR + (ch ^ sw)] = lo;
@@ -368,33 +397,33 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int r = 0; r < 16; ++r) o[hb][t][r] = 0.0f;
-  float m_run[2] = {-INFINITY, -INFINITY}, l_run[2] = {0.0f, 0.0f};
-  const bf16x2_t ones = {(bf16)1.0f, (bf16)1.0f};
+  float l_run[2] = {0.0f, 0.0f};
+  float m_cur[2] = {0.0f, 0.0f};   // reference per query (log2 units), set on the first step
 
   const int key_end = sg.nf == 1 ? sg.n : seg_len;
   const int nsteps = (key_end + KS - 1) / KS;
   const int ntiles = (nsteps + 3) / 4;
-  load_tile(0);
-  store_tile(0);
-  __syncthreads();
-  load_tile(ntiles > 1 ? KT : 0);
 
-  f32x16 s_next[2];
-  qk_step(sK[0], 0, l32, g, qf, s_next);
-
-  for (int st = 0; st < nsteps; ++st) {
-    const int tile = st >> 2, sub = st & 3, cur = tile & 1;
+  // K fragments of step `sub` of an LDS tile (row l32 of the step's 32 keys, k-group g)
+  auto load_kf = [&](int cur, int sub, u32x4 (&kf)[4]) {
+    const int krow = sub * KS + l32;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) kf[f] = sK[cur][krow * KCPR + ((2 * f + g) ^ ((krow >> 1) & 7))];
+  };
+  // one 32-key step: S^T, mask, then per query block softmax and PV
+  auto step = [&](int cur, int sub, int st) {
     const int k0 = st * KS;
-    f32x16 s[2] = {s_next[0], s_next[1]};
-    if (st + 1 < nsteps) {
-      if (sub == 3) {   // the next step is in the next tile: publish it
-        __syncthreads();
-        store_tile(cur ^ 1);
-        __syncthreads();
-        load_tile(tile + 2 < ntiles ? (tile + 2) * KT : 0);
-      }
-      const int nx = st + 1;
-      qk_step(sK[(nx >> 2) & 1], (nx & 3) * KS, l32, g, qf, s_next);
+    u32x4 kf[4];
+    load_kf(cur, sub, kf);
+    f32x16 s[2];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[hb][r] = 0.0f;
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+        s[hb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf[f], *(const bf16x8*)&qf[hb][f], s[hb],
+                                                        0, 0, 0);
     }
     // mask keys outside the segment or in the padding rows between frames
     const int f0 = k0 / sg.npad;
@@ -408,68 +437,76 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
         s[1][r] = ok ? s[1][r] : -INFINITY;
       }
     }
-    // running max: moved only when a step's max exceeds it by more than 8 (log2 units)
-    float mx[2];
+    // V^T fragments of the step, shared by both query blocks
+    u32x4 vf[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int drow = t * 32 + l32;
+#pragma unroll
+      for (int j2 = 0; j2 < 2; ++j2) vf[t][j2] = sV[cur][drow * VCPR + ((4 * sub + 2 * j2 + g) ^ (drow & 15))];
+    }
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
-      float a = s[hb][0];
+      u32x4 pf[2];
+      float ls;
+      probs(s[hb], m_cur[hb], pf, ls);
+      // (re)establish the reference on the first step, or when the probabilities grew large
+      if (__any(st == 0 || !(ls <= GROW))) {
+        float mx = s[hb][0];
 #pragma unroll
-      for (int r = 1; r < 16; ++r) a = fmaxf(a, s[hb][r]);
-      a = fmaxf(a, __shfl_xor(a, 32, 64));
-      mx[hb] = a * c;
-    }
-    const bool grow = (mx[0] > m_run[0] + 8.0f) || (mx[1] > m_run[1] + 8.0f);
-    if (__any(grow)) {
-#pragma unroll
-      for (int hb = 0; hb < 2; ++hb) {
-        const float m_new = fmaxf(m_run[hb], mx[hb]);
-        const float alpha = m_new == -INFINITY ? 1.0f : fast_exp2(m_run[hb] - m_new);
-        m_run[hb] = m_new;
+        for (int r = 1; r < 16; ++r) mx = fmaxf(mx, s[hb][r]);
+        mx = pair_max(mx);
+        const float m_old = m_cur[hb];
+        float m_new = st == 0 ? mx : fmaxf(m_old, mx);
+        m_new = m_new > -INFINITY ? m_new : 0.0f;   // a step with every key masked keeps a finite m
+        const float alpha = st == 0 ? 1.0f : fast_exp2(m_old - m_new);
+        m_cur[hb] = m_new;
         l_run[hb] *= alpha;
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
           for (int r = 0; r < 16; ++r) o[hb][t][r] *= alpha;
+        probs(s[hb], m_new, pf, ls);
       }
-    }
-    // probabilities (bf16, B operand of PV) and their row sums
-    u32x4 pf[2][2];
-#pragma unroll
-    for (int hb = 0; hb < 2; ++hb) {
-      const float nm = -m_run[hb];
-      float ls = 0.0f;
-#pragma unroll
-      for (int j2 = 0; j2 < 2; ++j2)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const f32x2 e = {fast_exp2(fmaf(s[hb][8 * j2 + 2 * q], c, nm)),
-                           fast_exp2(fmaf(s[hb][8 * j2 + 2 * q + 1], c, nm))};
-          const bf16x2_t pr = __builtin_convertvector(e, bf16x2_t);
-          ls = __builtin_amdgcn_fdot2_f32_bf16(pr, ones, ls, false);
-          pf[hb][j2][q] = __builtin_bit_cast(unsigned, pr);
-        }
       l_run[hb] += ls;
-    }
-    // O^T += V^T P^T for this step's 32 keys; V fragments shared by both query blocks
+      // O^T += V^T P^T for this block
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int drow = t * 32 + l32;
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int j2 = 0; j2 < 2; ++j2) {
-        const u32x4 vf = sV[cur][drow * VCPR + ((4 * sub + 2 * j2 + g) ^ (drow & 15))];
-#pragma unroll
-        for (int hb = 0; hb < 2; ++hb)
-          o[hb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&vf, *(const bf16x8*)&pf[hb][j2],
+        for (int j2 = 0; j2 < 2; ++j2)
+          o[hb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&vf[t][j2], *(const bf16x8*)&pf[j2],
                                                              o[hb][t], 0, 0, 0);
+    }
+  };
+
+  load_k(0);
+  store_k(0);
+  load_v(0);
+  store_v(0);
+  __syncthreads();
+  for (int tile = 0; tile < ntiles; ++tile) {
+    const int cur = tile & 1, st0 = tile * 4;
+    const bool more = tile + 1 < ntiles;
+    const int kt_next = (tile + 1) * KT;
+    if (more) load_k(kt_next);
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub) {
+      if (st0 + sub < nsteps) step(cur, sub, st0 + sub);
+      if (sub == 1 && more) {
+        store_k(cur ^ 1);
+        load_v(kt_next);
       }
+    }
+    if (more) {
+      store_v(cur ^ 1);
+      __syncthreads();
     }
   }
 
 #pragma unroll
   for (int hb = 0; hb < 2; ++hb) {
     const int qrow = qbase + hb * 32 + l32;
-    const float l_tot = l_run[hb] + __shfl_xor(l_run[hb], 32, 64);
-    const float inv = 1.0f / l_tot;
+    const float inv = 1.0f / pair_sum(l_run[hb]);
     if (qrow < seg_len) {
       bf16* orow = O + (int64_t)(sg.base + qrow) * dim + h * HD;
 #pragma unroll
@@ -484,7 +521,7 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v2(const bf16* __restrict_
     }
   }
 }
-}  // namespace v2
+}  // namespace v3
 
 template <typename T, int HD>
 static hipError_t launch(const void* q, const void* k, const void* vt, void* o, int64_t mpad,
@@ -498,7 +535,7 @@ static hipError_t launch(const void* q, const void* k, const void* vt, void* o, 
   return hipGetLastError();
 }
 
-int attention_q_tile(Dtype dt, int hd) { return (dt == DT_BF16 && hd == 64) ? v2::QT : 128; }
+int attention_q_tile(Dtype dt, int hd) { return (dt == DT_BF16 && hd == 64) ? v3::QT : 128; }
 
 hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void* vt, void* o,
                      int64_t mpad, int heads, int dim, const AttnSeg* segs, const AttnWork* work,
@@ -507,7 +544,7 @@ hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void*
     if (hd == 64) {
       if (nwork <= 0) return hipSuccess;
       const float c = (float)(1.4426950408889634 / 8.0);
-      hipLaunchKernelGGL(v2::attn_kernel_v2, dim3(nwork * heads), dim3(256), 0, s, (const bf16*)q, (const bf16*)k,
+      hipLaunchKernelGGL(v3::attn_kernel_v3, dim3(nwork * heads), dim3(256), 0, s, (const bf16*)q, (const bf16*)k,
                          (const bf16*)vt, (bf16*)o, mpad, heads, dim, segs, work, nwork, c);
       return hipGetLastError();
     }
