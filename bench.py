@@ -22,6 +22,32 @@ sys.path.insert(0, ROOT)
 import mf_synth  # noqa: E402
 
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "attn_global_small_traffic.md")
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2601_07154_amd", "csrc", f) for f in ("attention.hip", "device.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per global-attention launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, if it was taken on the current kernel source (else None)."""
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    src = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not src or not val or src.group(1) != kernel_source_hash():
+        return None
+    return float(val.group(1))
 
 
 def window_sizes(n_frames: int, window: int, overlap: int) -> list:
@@ -181,6 +207,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--sigma", type=float, default=1000.0)
+    ap.add_argument("--source-hash", action="store_true", help="print the attention source hash and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (an elementwise torch kernel) so that HBM counters "
                          "of the same profiler run can be scaled by a transfer of known size")
@@ -191,6 +218,9 @@ def main():
     ap.add_argument("--serve-paced", action="store_true")
     ap.add_argument("--serve-fp32-streams", type=int, default=2)
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
@@ -199,11 +229,16 @@ def main():
         return
     wl = mf_synth.SMALL
     if args.copy_calibration:
+        # a plain copy of known size for the HBM counters: 1 GiB read and 1 GiB written by one
+        # kernel, after 1 GiB of other writes has pushed the source out of the caches
         import torch
-        src = torch.ones(64 << 20, device="cuda", dtype=torch.float32)   # 256 MiB
+        src = torch.ones(256 << 20, device="cuda", dtype=torch.float32)
+        flush = torch.zeros(256 << 20, device="cuda", dtype=torch.float32)
         dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)                                      # one kernel: reads and writes 256 MiB
         torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, flush, dst
     r = run_gpu(wl, args.precision, args.steps, args.warmup, args.sigma)
     fps = r["frames"] / r["seconds"]
     rg = run_gpu(wl, args.precision, args.steps, args.warmup, args.sigma, profile=False, graphs=True)
@@ -229,7 +264,8 @@ def main():
     ach = flops / (avg_ms * 1e-3) / 1e12
     res["roofline"] = {"kernel": "global flash attention (attn_kernel_v3, bf16, hd 64)", "bound": "mfma",
                        "achieved": ach, "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
-                       "frac": ach / PEAK_TFLOPS[args.precision], "traffic": None,
+                       "frac": ach / PEAK_TFLOPS[args.precision],
+                       "traffic": measured_traffic() if args.precision == "bf16" else None,
                        "avg_launch_ms": avg_ms, "launches": prof["attn_global_calls"],
                        "flops_per_launch": flops}
     res["stage_ms_per_step"] = {"attn_global": prof["attn_global_ms"] / args.steps,

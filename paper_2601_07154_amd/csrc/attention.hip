@@ -121,7 +121,9 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
 
   const int nb = nwork * heads;
   const int bid = xcd_remap(blockIdx.x, nb);
-  const int h = bid % heads, wi = bid / heads;
+  // head-major: the query tiles of one segment and head are consecutive, so the workgroups an XCD
+  // runs together share that head's K and V in its L2
+  const int h = bid / nwork, wi = bid - h * nwork;
   const AttnWork wk = work[wi];
   const AttnSeg sg = segs[wk.seg];
   const int seg_len = sg.nf * sg.npad;
@@ -329,7 +331,9 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
   __shared__ u32x4 sV[2][HD * VCPR];
   const int nb = nwork * heads;
   const int bid = xcd_remap(blockIdx.x, nb);
-  const int h = bid % heads, wi = bid / heads;
+  // head-major: the query tiles of one segment and head are consecutive, so the workgroups an XCD
+  // runs together share that head's K and V in its L2
+  const int h = bid / nwork, wi = bid - h * nwork;
   const AttnWork wk = work[wi];
   const AttnSeg sg = segs[wk.seg];
   const int seg_len = sg.nf * sg.npad;
