@@ -68,6 +68,12 @@ def global_attention_flops(wl) -> float:
     return sum(4.0 * (S * n) ** 2 * wl.model.dim for S in window_sizes(wl.frames, wl.window, wl.overlap))
 
 
+def gemm_flops(wl) -> float:
+    """Algorithmic flops of the transformer GEMMs (QKV, out-projection, fc1, fc2) of one step."""
+    n, D, F, L = wl.tokens_per_frame, wl.model.dim, wl.model.mlp, wl.model.depth
+    return sum(L * 2.0 * S * n * D * (3 * D + D + 2 * F) for S in window_sizes(wl.frames, wl.window, wl.overlap))
+
+
 def path_flops(wl) -> float:
     n, D, F, L = wl.tokens_per_frame, wl.model.dim, wl.model.mlp, wl.model.depth
     tot = 0.0
@@ -130,8 +136,8 @@ def run_gpu(wl, precision: str, steps: int, warmup: int, sigma: float, profile: 
 
 
 def cpu_baseline(wl, sigma: float):
-    """The FP64 oracle on a bounded sample: window 0 (16 frames, all layers) plus chaining, focus
-    and maps of its frames; frames/s extrapolated to the whole stream (7 windows per 64 frames)."""
+    """The FP64 oracle on a bounded sample: window 0 (all layers) plus chaining, focus and maps of
+    its frames; frames/s extrapolated to the whole stream (its windows per its frames)."""
     from oracle import pipeline, vit
     blob = mf_synth.make_weights(wl.model, wl.seed_weights)
     w = vit.unpack_weights(blob, wl.model.depth, wl.model.dim, wl.model.mlp)
@@ -206,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
+    ap.add_argument("--workload", default="small", choices=["small", "large", "fp8"],
+                    help="small (the headline line) or one of the larger configurations (no FP32 leg, no CPU baseline)")
     ap.add_argument("--sigma", type=float, default=1000.0)
     ap.add_argument("--source-hash", action="store_true", help="print the attention source hash and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -227,7 +235,10 @@ def main():
     if args.serve:
         run_serve(args)
         return
-    wl = mf_synth.SMALL
+    wl = {"small": mf_synth.SMALL, "large": mf_synth.LARGE, "fp8": mf_synth.FP8}[args.workload]
+    if args.workload != "small":
+        args.no_fp32 = True
+        args.no_cpu_baseline = True
     if args.copy_calibration:
         # a plain copy of known size for the HBM counters: 1 GiB read and 1 GiB written by one
         # kernel, after 1 GiB of other writes has pushed the source out of the caches
@@ -271,6 +282,10 @@ def main():
     res["stage_ms_per_step"] = {"attn_global": prof["attn_global_ms"] / args.steps,
                                 "attn_frame": prof["attn_frame_ms"] / args.steps,
                                 "gemm": prof["gemm_ms"] / args.steps}
+    if prof["gemm_ms"] > 0:
+        gt = gemm_flops(wl) / (prof["gemm_ms"] / args.steps * 1e-3) / 1e12
+        res["gemm_tflops"] = gt
+        res["gemm_mfma_frac"] = gt / PEAK_TFLOPS[args.precision]
     if not args.no_fp32 and args.precision != "fp32":
         f = run_gpu(wl, "fp32", 2, 1, args.sigma)
         res["fp32_value"] = f["frames"] / f["seconds"]
@@ -282,10 +297,11 @@ def main():
         res["speedup_fp8_vs_bf16_graphs"] = res["fp8_value"] / res["value_graphs_unprofiled"]
     if not args.no_cpu_baseline:
         cfps, cdt, out = cpu_baseline(wl, args.sigma)
+        nwin = len(window_sizes(wl.frames, wl.window, wl.overlap))
         res["cpu_baseline"] = {"value": cfps, "unit": "frames/s", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                                "kind": "oracle",
-                               "sample": f"window 0 of the workload (16 frames, all 12 layers, FP64) + anchoring/focus/maps: "
-                                         f"{cdt:.1f} s, scaled to 7 windows per 64 frames"}
+                               "sample": f"window 0 of the workload ({wl.window} frames, all {wl.model.depth} layers, FP64) + "
+                                         f"anchoring/focus/maps: {cdt:.1f} s, scaled to {nwin} windows per {wl.frames} frames"}
         # pose error of the timed GPU run against the FP64 oracle on window 0
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         from gpu_util import dir_err_deg, rot_err_deg
