@@ -273,8 +273,8 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
 // staged in LDS tiles of 128 (double-buffered, one barrier per tile; the next tile passes
 // through 16 registers per thread, K during the first steps, V after) and consumed in 32-key
 // steps, unrolled four to a tile so every LDS offset is a constant.  Per step:
-//  - S^T = K Q^T with Q pre-scaled by log2(e)/sqrt(hd) once per workgroup, so the exp2 argument
-//    is s - m for the query's reference m;
+//  - S^T = K Q^T; the exp2 argument s c - m (c = log2(e)/sqrt(hd), m the query's reference in
+//    log2 units) is one fma per score;
 //  - m is set from the query's first-step maximum and raised only when a step's probabilities
 //    grow large (a lane's partial row sum above 2^12, which also catches an overflow to inf);
 //    no per-step maximum is computed otherwise, and the O rescale is rare;
@@ -304,16 +304,16 @@ MF_DEV float pair_sum(float v) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// p = exp2(s - m) as bf16 pairs (the B operand of PV, keys 4g.., 8+4g.. per 16-key half) and the
+// p = exp2(s c - m) as bf16 pairs (the B operand of PV, keys 4g.., 8+4g.. per 16-key half) and the
 // lane's partial row sum over those probabilities
-MF_DEV void probs(const f32x16& s, float m, u32x4 (&pf)[2], float& ls) {
+MF_DEV void probs(const f32x16& s, float c, float m, u32x4 (&pf)[2], float& ls) {
   const bf16x2_t ones = {(bf16)1.0f, (bf16)1.0f};
   float acc = 0.0f;
 #pragma unroll
   for (int j2 = 0; j2 < 2; ++j2)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const f32x2 e = {fast_exp2(s[8 * j2 + 2 * q] - m), fast_exp2(s[8 * j2 + 2 * q + 1] - m)};
+      const f32x2 e = {fast_exp2(fmaf(s[8 * j2 + 2 * q], c, -m)), fast_exp2(fmaf(s[8 * j2 + 2 * q + 1], c, -m))};
       const bf16x2_t pr = __builtin_convertvector(e, bf16x2_t);
       acc = __builtin_amdgcn_fdot2_f32_bf16(pr, ones, acc, false);
       pf[j2][q] = __builtin_bit_cast(unsigned, pr);
@@ -345,19 +345,12 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
   const bf16* Kh = K + ((int64_t)h * mpad + sg.base) * HD;
   const bf16* Vh = Vt + (int64_t)h * HD * mpad + sg.base;
 
-  // Q fragments, scaled to log2 units (one extra bf16 rounding of q * c)
   u32x4 qf[2][4];
 #pragma unroll
   for (int hb = 0; hb < 2; ++hb) {
     const u32x4* qr = (const u32x4*)(Qh + (int64_t)(qbase + hb * 32 + l32) * HD);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const u32x4 raw = qr[2 * f + g];
-      bf16x8 v = *(const bf16x8*)&raw;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (bf16)((float)v[e] * c);
-      qf[hb][f] = *(const u32x4*)&v;
-    }
+    for (int f = 0; f < 4; ++f) qf[hb][f] = qr[2 * f + g];
   }
 
   // K tile: thread -> row tid/2, chunks 4 (tid%2) .. +3.  V^T tile: thread -> row tid/4, keys
@@ -453,13 +446,13 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
     for (int hb = 0; hb < 2; ++hb) {
       u32x4 pf[2];
       float ls;
-      probs(s[hb], m_cur[hb], pf, ls);
+      probs(s[hb], c, m_cur[hb], pf, ls);
       // (re)establish the reference on the first step, or when the probabilities grew large
       if (__any(st == 0 || !(ls <= GROW))) {
         float mx = s[hb][0];
 #pragma unroll
         for (int r = 1; r < 16; ++r) mx = fmaxf(mx, s[hb][r]);
-        mx = pair_max(mx);
+        mx = pair_max(mx) * c;
         const float m_old = m_cur[hb];
         float m_new = st == 0 ? mx : fmaxf(m_old, mx);
         m_new = m_new > -INFINITY ? m_new : 0.0f;   // a step with every key masked keeps a finite m
@@ -470,7 +463,7 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
         for (int t = 0; t < 2; ++t)
 #pragma unroll
           for (int r = 0; r < 16; ++r) o[hb][t][r] *= alpha;
-        probs(s[hb], m_new, pf, ls);
+        probs(s[hb], c, m_new, pf, ls);
       }
       l_run[hb] += ls;
       // O^T += V^T P^T for this block

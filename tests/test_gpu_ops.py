@@ -96,6 +96,78 @@ def test_attention_rows_sum_to_one(prec, tol):
     np.testing.assert_allclose(got[valid], 1.0, atol=tol)
 
 
+def _scored_case(torch, prec, kind, hd=64, heads=2, frames=3, n=300, seed=21):
+    """Q, K whose scores follow a chosen pattern along the keys of a 3-frame segment, V random.
+
+    growing:  scores rise ~0.23 log2 units per key (200+ over the segment), so the reference
+              maximum must be raised many times after the first step;
+    falling:  the same, decreasing (the first step holds the maximum, later probabilities vanish);
+    negative: every score near -200 log2 units (the reference must come from the first step's
+              maximum, not from 0, or every probability underflows);
+    spike:    random scores plus one key per frame 40 log2 units above the rest, late in the frame."""
+    rng = np.random.default_rng(seed)
+    npad = (n + 7) // 8 * 8
+    mpad = frames * npad + 256 + 64
+    q = np.zeros((heads, mpad, hd), np.float32)
+    k = np.zeros((heads, mpad, hd), np.float32)
+    v = rng.normal(size=(heads, mpad, hd)).astype(np.float32)
+    rows = np.concatenate([np.arange(f * npad, f * npad + n) for f in range(frames)])
+    j = np.arange(len(rows), dtype=np.float32)
+    if kind in ("growing", "falling"):
+        a = 0.02 * (j if kind == "growing" else j[::-1])
+        q[:, rows] = 1.0 + 0.1 * rng.normal(size=(heads, len(rows), hd))
+        k[:, rows] = a[None, :, None] + 0.1 * rng.normal(size=(heads, len(rows), hd))
+    elif kind == "negative":
+        q[:, rows] = 4.16 + 0.05 * rng.normal(size=(heads, len(rows), hd))
+        k[:, rows] = -4.16 + 0.3 * rng.normal(size=(heads, len(rows), hd))
+    else:
+        q[:, rows] = rng.normal(size=(heads, len(rows), hd))
+        k[:, rows] = rng.normal(size=(heads, len(rows), hd))
+        for f in range(frames):
+            r = f * npad + n - 5
+            k[:, r] = q[:, f * npad] * 0.0 + 3.0 * np.sign(q[:, f * npad + 1])
+    if prec == "bf16":
+        q, k, v = round_bf16(q), round_bf16(k), round_bf16(v)
+    tdt = torch.bfloat16 if prec == "bf16" else torch.float32
+    dq = torch.from_numpy(q).to("cuda", tdt).contiguous()
+    dk = torch.from_numpy(k).to("cuda", tdt).contiguous()
+    dvt = torch.from_numpy(np.ascontiguousarray(v.transpose(0, 2, 1))).to("cuda", tdt).contiguous()
+    do = torch.zeros((mpad, hd * heads), device="cuda", dtype=tdt)
+    return (q.astype(np.float64), k.astype(np.float64), v.astype(np.float64), dq, dk, dvt, do, npad, mpad, rows)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("kind", ["growing", "falling", "negative", "spike"])
+def test_attention_score_ranges(prec, tol, kind):
+    """The reference-maximum logic of the softmax (set on a query's first key step, raised when a
+    step's probabilities grow large) against the FP64 oracle, on score patterns that exercise it;
+    frame-wise and global segments.  Errors are relative to max |V|."""
+    torch = torch_cuda()
+    m = mf()
+    hd, heads, frames, n = 64, 2, 3, 300
+    q, k, v, dq, dk, dvt, do, npad, mpad, rows = _scored_case(torch, prec, kind, hd, heads, frames, n)
+    s_max = max(np.abs(q[h, rows] @ k[h, rows].T).max() for h in range(heads)) / np.sqrt(hd) * np.log2(np.e)
+    print(f"{kind}: max |score| {s_max:.0f} log2 units")
+    vmax = np.abs(v).max()
+    m.op_attention(prec, hd, heads, hd * heads, dq, dk, dvt, do, mpad, [[0, frames, n, npad]])
+    got = do.float().cpu().numpy()
+    assert np.isfinite(got[rows]).all()
+    for h in range(heads):
+        ref = vit.attention(q[h, rows], k[h, rows], v[h, rows])
+        err = np.abs(got[rows, h * hd:(h + 1) * hd] - ref).max() / vmax
+        assert err < tol, (kind, h, err)
+    do.zero_()
+    segs = [[f * npad, 1, n, npad] for f in range(frames)]
+    m.op_attention(prec, hd, heads, hd * heads, dq, dk, dvt, do, mpad, segs)
+    got = do.float().cpu().numpy()
+    for f in range(frames):
+        r = slice(f * npad, f * npad + n)
+        for h in range(heads):
+            ref = vit.attention(q[h, r], k[h, r], v[h, r])
+            err = np.abs(got[r, h * hd:(h + 1) * hd] - ref).max() / vmax
+            assert err < tol, (kind, "frame", f, h, err)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 3e-6), ("bf16", 1e-2)])
 @pytest.mark.parametrize("dim", [128, 384, 1024])
 def test_layernorm(prec, tol, dim):
