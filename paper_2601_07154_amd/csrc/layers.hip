@@ -219,19 +219,23 @@ __global__ void fill_u32_kernel(unsigned* p, int n, unsigned v) {
 }
 
 // Per-window amax of bf16 rows [rows][C] over the valid (non-padding) token rows of each window.
-// Block (x, w): rows base + 16 x .. +15 of window w; 16 threads per row.
+// Block (x, w) of gridDim.x per window: rows base + 16 x + 16 gridDim.x k of window w (16 threads
+// per row), reduced in the block to one atomicMax: about a thousand atomics per launch instead of
+// one per 16 rows.
 __global__ __launch_bounds__(256) void window_amax_kernel(const bf16* __restrict__ y, int C,
                                                           const AttnSeg* __restrict__ wins,
                                                           unsigned* __restrict__ amax) {
   const AttnSeg w = wins[blockIdx.y];
-  const int rel = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int rows = w.nf * w.npad;
   float mx = 0.0f;
-  if (rel < w.nf * w.npad && (rel % w.npad) < w.n) {
-    const bf16* row = y + (int64_t)(w.base + rel) * C;
-    for (int c = (threadIdx.x & 15) * 8; c < C; c += 128) {
-      const bf16x8 v = *(const bf16x8*)(row + c);
+  for (int rel = blockIdx.x * 16 + (threadIdx.x >> 4); rel < rows; rel += gridDim.x * 16) {
+    if ((rel % w.npad) < w.n) {
+      const bf16* row = y + (int64_t)(w.base + rel) * C;
+      for (int c = (threadIdx.x & 15) * 8; c < C; c += 128) {
+        const bf16x8 v = *(const bf16x8*)(row + c);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf((float)v[e]));
+        for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf((float)v[e]));
+      }
     }
   }
   mx = wave_max(mx);
@@ -278,9 +282,12 @@ hipError_t window_quant_fp8(const bf16* y, int C, const AttnSeg* wins, int nwin,
   if (nwin <= 0) return hipSuccess;
   if (C % 16 != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fill_u32_kernel, dim3((nwin + 255) / 256), dim3(256), 0, s, amax, nwin, 0u);
-  const dim3 grid((unsigned)((max_rows + 15) / 16), (unsigned)nwin);
-  hipLaunchKernelGGL(window_amax_kernel, grid, dim3(256), 0, s, y, C, wins, amax);
-  hipLaunchKernelGGL(window_quant_kernel, grid, dim3(256), 0, s, y, C, wins, amax, q, srow);
+  const int xb = (max_rows + 15) / 16;
+  const int per_win = 1024 / nwin > 16 ? 1024 / nwin : 16;
+  hipLaunchKernelGGL(window_amax_kernel, dim3((unsigned)(xb < per_win ? xb : per_win), (unsigned)nwin), dim3(256),
+                     0, s, y, C, wins, amax);
+  hipLaunchKernelGGL(window_quant_kernel, dim3((unsigned)xb, (unsigned)nwin), dim3(256), 0, s, y, C, wins, amax, q,
+                     srow);
   return hipGetLastError();
 }
 
