@@ -480,6 +480,13 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
   store_k(0);
   load_v(0);
   store_v(0);
+  // The Q fragments must have landed before the loop: left pending, they make the compiler wait
+  // on vmcnt before each S^T MFMA inside the loop, which (loads retire in order) also waits for
+  // the next tile's K/V prefetch.  The empty asm consumes them here.
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+    for (int f = 0; f < 4; ++f) asm volatile("" : : "v"(qf[hb][f]));
   __syncthreads();
   for (int tile = 0; tile < ntiles; ++tile) {
     const int cur = tile & 1, st0 = tile * 4;
