@@ -74,7 +74,7 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
     nbase = (n0 / D) * D;
     dst = (To*)(which == 0 ? a.q : (which == 1 ? a.k : a.vt));
   }
-  static_assert(WN == 2, "the staged epilogue assumes 64 columns per wave");
+  static_assert(WN % 2 == 0, "the staged epilogue takes a wave's columns 64 at a time");
   if constexpr (EPI == EPI_PATCH) {
     // once per batch: direct stores. rowinfo bits 30-31: 0 patch, 1 reference camera, 2 other
     // camera, 3 padding; low bits the position-code row
@@ -106,7 +106,9 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
     constexpr int SR = 68;   // floats per staged row: 16-byte aligned, rows 4 banks apart
     float* stage = (float*)smem + wave * (32 * SR);
     const int rr = lane >> 4, c4 = (lane & 15) * 4;
-    const int nb = n0 + wc * 64 + c4;
+#pragma unroll
+    for (int jh = 0; jh < WN / 2; ++jh) {
+    const int nb = n0 + wc * 32 * WN + jh * 64 + c4;
     f32x4 bias4 = {0.0f, 0.0f, 0.0f, 0.0f};
     if (a.bias) bias4 = *(const f32x4*)(a.bias + nb);
     int64_t qoff = 0;   // QKV: head-major offset of column nb (4 columns stay within one head)
@@ -119,11 +121,12 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
     for (int i = 0; i < WM; ++i) {
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < WN; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int rg = 0; rg < 4; ++rg)
           *(f32x4*)(stage + l32 * SR + j * 32 + 8 * rg + 4 * g) =
-              (f32x4){acc[i][j][4 * rg], acc[i][j][4 * rg + 1], acc[i][j][4 * rg + 2], acc[i][j][4 * rg + 3]};
+              (f32x4){acc[i][2 * jh + j][4 * rg], acc[i][2 * jh + j][4 * rg + 1], acc[i][2 * jh + j][4 * rg + 2],
+                      acc[i][2 * jh + j][4 * rg + 3]};
       __syncthreads();
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
@@ -156,6 +159,7 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
         }
       }
     }
+    }
   } else {
     // V^T of the QKV projection (lane = column, 4 consecutive rows per register group): staged
     // transposed, [column][row], so that 8 lanes read one column's 32 consecutive rows = keys.
@@ -164,14 +168,17 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
     float* stage = (float*)smem + wave * (64 * SV);
     const int cc = lane >> 3, r4 = (lane & 7) * 4;
 #pragma unroll
+    for (int jh = 0; jh < WN / 2; ++jh)
+#pragma unroll
     for (int i = 0; i < WM; ++i) {
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < WN; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int rg = 0; rg < 4; ++rg)
           *(f32x4*)(stage + (j * 32 + l32) * SV + 8 * rg + 4 * g) =
-              (f32x4){acc[i][j][4 * rg], acc[i][j][4 * rg + 1], acc[i][j][4 * rg + 2], acc[i][j][4 * rg + 3]};
+              (f32x4){acc[i][2 * jh + j][4 * rg], acc[i][2 * jh + j][4 * rg + 1], acc[i][2 * jh + j][4 * rg + 2],
+                      acc[i][2 * jh + j][4 * rg + 3]};
       __syncthreads();
       const int mb = m0 + wr * 32 * WM + i * 32 + r4;
       float sc[4];
@@ -180,7 +187,7 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         const int c = cc + 8 * p;
-        const int n = n0 + wc * 64 + c;
+        const int n = n0 + wc * 32 * WN + jh * 64 + c;
         const int nn = n - nbase;
         const int h = nn / a.hd, d = nn - h * a.hd;
         const float bn = a.bias[n];
@@ -429,6 +436,10 @@ template <typename T, int EPI, int WM, int WN, int TC>
 static hipError_t launch_tile(const GemmArgs& a, hipStream_t s) {
   constexpr int BM = 64 * WM, BN = 64 * WN;
   if (a.M <= 0 || a.N <= 0) return hipSuccess;
+  if (a.N % BN != 0) return hipErrorInvalidValue;
+  // the epilogue resolves the q / k / v destination once per tile: a tile must not straddle blocks
+  if constexpr (EPI == EPI_QKV)
+    if ((a.heads * a.hd) % BN != 0) return hipErrorInvalidValue;
   const int nb = ((a.M + BM - 1) / BM) * (a.N / BN);
   // bf16 / fp32: direct-to-LDS main loop; fp8: register-staged (measured faster for E4M3)
   if constexpr (sizeof(T) == 1) hipLaunchKernelGGL((gemm_kernel<T, WM, WN, EPI, TC>), dim3(nb), dim3(256), 0, s, a);
