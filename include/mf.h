@@ -104,6 +104,11 @@ typedef struct mf_focus {
   double u, v;              /* Eq. 6 */
   double s;                 /* |a_world|, the motion magnitude of Eq. 7 */
   double t_push, t_ready;   /* seconds since engine creation: frame pushed / result complete */
+  double t_window;          /* the frame's window became complete (its last frame pushed; for the
+                               tail or only window of a stream, also its end of stream) */
+  double t_batch;           /* the batch that computed the window started: latency t_ready - t_push
+                               = buffering (t_window - t_push) + queueing (t_batch - t_window) +
+                               compute (t_ready - t_batch) */
 } mf_focus;
 
 typedef struct mf_stats {

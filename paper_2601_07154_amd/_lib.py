@@ -44,7 +44,8 @@ class Focus(C.Structure):
                 ("T_w2c", C.c_double * 16), ("pose9", C.c_float * 9), ("peak_x", C.c_int32),
                 ("peak_y", C.c_int32), ("reserved", C.c_float), ("a_world", C.c_double * 3),
                 ("a_cam", C.c_double * 3), ("u", C.c_double), ("v", C.c_double), ("s", C.c_double),
-                ("t_push", C.c_double), ("t_ready", C.c_double)]
+                ("t_push", C.c_double), ("t_ready", C.c_double), ("t_window", C.c_double),
+                ("t_batch", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -56,13 +57,13 @@ class Stats(C.Structure):
 
 FOCUS_DTYPE = np.dtype({
     "names": ["frame", "window", "valid", "T_w2c", "pose9", "peak_x", "peak_y", "a_world", "a_cam",
-              "u", "v", "s", "t_push", "t_ready"],
+              "u", "v", "s", "t_push", "t_ready", "t_window", "t_batch"],
     "formats": ["<i8", "<i4", "<i4", ("<f8", (16,)), ("<f4", (9,)), "<i4", "<i4", ("<f8", (3,)),
-                ("<f8", (3,)), "<f8", "<f8", "<f8", "<f8", "<f8"],
+                ("<f8", (3,)), "<f8", "<f8", "<f8", "<f8", "<f8", "<f8", "<f8"],
     "offsets": [Focus.frame.offset, Focus.window.offset, Focus.valid.offset, Focus.T_w2c.offset,
                 Focus.pose9.offset, Focus.peak_x.offset, Focus.peak_y.offset, Focus.a_world.offset,
                 Focus.a_cam.offset, Focus.u.offset, Focus.v.offset, Focus.s.offset, Focus.t_push.offset,
-                Focus.t_ready.offset],
+                Focus.t_ready.offset, Focus.t_window.offset, Focus.t_batch.offset],
     "itemsize": C.sizeof(Focus),
 })
 

@@ -50,6 +50,7 @@ struct Stream {
   int64_t pushed = 0;           // frames (or poses) received
   int64_t ring_lo = 0;          // oldest frame a future window may still read
   bool eos = false;
+  double eos_time = 0.0;        // when eos was set
   int64_t next_start = 0;       // start of the next regular window
   int32_t next_k = 0;           // windows scheduled so far
   int64_t emitted_end = 0;      // frames scheduled for emission so far
@@ -234,6 +235,7 @@ static int step(Engine& e) {
   std::vector<mf_focus> out;
   std::string err;
   double ms = 0.0;
+  const double t_batch = e.now();
   const mf_status rc = e.ex->run_batch(b, out, &ms, err);
   const double t_ready = e.now();
 
@@ -248,10 +250,19 @@ static int step(Engine& e) {
   size_t k = 0;
   for (auto& w : b.wins) {
     Stream& s = *e.streams.at(w.stream_id);
+    // the window was complete when its last frame arrived; a window cut short by the end of the
+    // stream (tail or only window) also needed the end of stream
+    const int64_t tl = w.emit_end - 1 - s.push_time_base;
+    double t_window = (tl >= 0 && tl < (int64_t)s.push_time.size()) ? s.push_time[tl] : 0.0;
+    const int stride = s.cfg.window - s.cfg.overlap;
+    const bool regular = s.kind == 1 && w.size == s.cfg.window && stride > 0 && w.start % stride == 0;
+    if (!regular && s.eos) t_window = std::max(t_window, s.eos_time);
     for (int64_t t = w.emit_begin; t < w.emit_end; ++t, ++k) {
       mf_focus r = out[k];
       const int64_t ti = t - s.push_time_base;
       r.t_push = (ti >= 0 && ti < (int64_t)s.push_time.size()) ? s.push_time[ti] : 0.0;
+      r.t_window = std::max(t_window, r.t_push);
+      r.t_batch = std::max(t_batch, r.t_window);
       r.t_ready = t_ready;
       s.ready.push_back(r);
     }
@@ -526,7 +537,10 @@ mf_status mf_push_frames(mf_engine* e, int32_t stream_id, const float* rgb, int3
   for (int i = 0; i < n; ++i) s->push_time.push_back(t);
   s->pushed += n;
   e->st.frames_pushed += n;
-  if (flags & MF_EOS) s->eos = true;
+  if ((flags & MF_EOS) && !s->eos) {
+    s->eos = true;
+    s->eos_time = t;
+  }
   poke(*e);
   return MF_OK;
   GUARD_END
@@ -613,6 +627,7 @@ mf_status mf_push_poses(mf_engine* e, int32_t stream_id, const double* T, int32_
     s->pose_jobs.push_back(std::move(j));
   }
   if (flags & MF_EOS) {
+    if (!s->eos) s->eos_time = e->now();
     s->eos = true;
     s->windows_done = true;
   }
@@ -703,6 +718,7 @@ mf_status mf_close_stream(mf_engine* e, int32_t stream_id) {
     set_err("unknown stream %d", stream_id);
     return MF_ENOTFOUND;
   }
+  if (!s->eos) s->eos_time = e->now();
   s->eos = true;
   if (s->kind != 1) s->windows_done = true;
   poke(*e);

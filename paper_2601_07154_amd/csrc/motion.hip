@@ -137,6 +137,8 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
       r.valid = valid;
       r.t_push = 0.0;
       r.t_ready = 0.0;
+      r.t_window = 0.0;
+      r.t_batch = 0.0;
     }
     __syncthreads();
   }

@@ -6,8 +6,9 @@ their capture rate (or all at once in the throughput regime), and results are po
 engine's scheduler thread completes windows.  Every window that is ready when a batch starts
 joins that batch, whatever stream it belongs to.
 
-Reported per frame: latency = t_ready - t_push, split into buffering (waiting for the window's
-last frame), queueing and compute is left to the caller from the records' timestamps.
+Reported per frame: latency = t_ready - t_push, split into buffering (t_window - t_push: waiting
+for the window's last frame, or the end of the stream for a tail window), queueing (t_batch -
+t_window: waiting for a batch to start) and compute (t_ready - t_batch: the batch itself).
 """
 from __future__ import annotations
 
@@ -107,6 +108,17 @@ def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float
 
 
 def latency_summary(recs_list):
-    lat = np.concatenate([(r["t_ready"] - r["t_push"]) for r in recs_list if len(r)]) * 1e3
-    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "frames": int(lat.size)}
+    """p50 / p99 / mean per-frame latency in ms, and the same for its buffering, queueing and
+    compute parts."""
+    recs = [r for r in recs_list if len(r)]
+    cat = lambda f: np.concatenate([f(r) for r in recs]) * 1e3
+    lat = cat(lambda r: r["t_ready"] - r["t_push"])
+    out = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "frames": int(lat.size)}
+    for name, f in (("buffering", lambda r: r["t_window"] - r["t_push"]),
+                    ("queueing", lambda r: r["t_batch"] - r["t_window"]),
+                    ("compute", lambda r: r["t_ready"] - r["t_batch"])):
+        part = cat(f)
+        out[name] = {"p50_ms": float(np.percentile(part, 50)), "p99_ms": float(np.percentile(part, 99)),
+                     "mean_ms": float(part.mean())}
+    return out

@@ -35,7 +35,11 @@ def test_served_streams_equal_streams_alone():
     assert st["batches_run"] < st["windows_run"]          # windows of several streams shared batches
     lat = serving.latency_summary(out["records"])
     print(f"served {lat['frames']} frames in {st['batches_run']} batches, p50 {lat['p50_ms']:.1f} ms, "
-          f"p99 {lat['p99_ms']:.1f} ms")
+          f"p99 {lat['p99_ms']:.1f} ms (mean buffering {lat['buffering']['mean_ms']:.1f}, queueing "
+          f"{lat['queueing']['mean_ms']:.1f}, compute {lat['compute']['mean_ms']:.1f} ms)")
+    for r in out["records"]:
+        assert (r["t_push"] <= r["t_window"]).all() and (r["t_window"] <= r["t_batch"]).all()
+        assert (r["t_batch"] <= r["t_ready"]).all()
     for i, spec in enumerate(specs):
         eng1 = m.Engine.from_model(model, blob, precision="bf16", threaded=False, max_tokens=32768)
         alone = serving.serve(eng1, [serving.StreamSpec(0.0, spec.length, spec.height, spec.width)], pool, 8, 4, K,

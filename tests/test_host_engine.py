@@ -67,7 +67,14 @@ def test_schedule_and_ordering(hostlib, N, L, O, chunk):
         assert (sel["window"] == k).all()
         assert (sel["pose9"][:, 0] == w["start"]).all() and (sel["pose9"][:, 1] == w["size"]).all()
     np.testing.assert_array_equal(recs["T_w2c"][:, 3], np.arange(N))
-    assert (recs["t_ready"] >= recs["t_push"]).all()
+    # latency parts are ordered: pushed <= window complete <= batch start <= result ready
+    assert (recs["t_push"] <= recs["t_window"]).all() and (recs["t_window"] <= recs["t_batch"]).all()
+    assert (recs["t_batch"] <= recs["t_ready"]).all() and (recs["t_push"] > 0).all()
+    # a regular window is complete when its last frame is pushed; the tail window needs the EOS push
+    for k, w in enumerate(sched):
+        sel = recs[(recs["frame"] >= w["emit_begin"]) & (recs["frame"] < w["emit_end"])]
+        last = recs[recs["frame"] == w["start"] + w["size"] - 1]["t_push"][0]
+        assert (sel["t_window"] >= last).all()
     # drained and closed: ECLOSED once, then the id is released
     assert st == mfp.MF_ECLOSED
     with pytest.raises(mfp.MfError) as e:
@@ -282,5 +289,7 @@ def test_serving_loop_on_host_stub(hostlib):
         assert list(r["frame"]) == list(range(s.length))
     lat = serving.latency_summary(out["records"])
     assert lat["frames"] == sum(s.length for s in specs)
+    parts = lat["buffering"]["mean_ms"] + lat["queueing"]["mean_ms"] + lat["compute"]["mean_ms"]
+    assert abs(parts - lat["mean_ms"]) < 1e-6 * max(1.0, lat["mean_ms"])   # the split adds up
     assert out["stats"]["streams_pending"] > 0          # admission had to wait
     eng.close()
