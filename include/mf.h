@@ -73,6 +73,14 @@ typedef struct mf_runtime_cfg {
   void* stream;                 /* hipStream_t to run on, or NULL for an engine-owned stream */
   int32_t use_graphs;           /* 1: each batch shape is captured once as a hipGraph and replayed */
   int32_t reserved;
+  /* Optional device allocator (both or neither): every device buffer of the engine (weights,
+     workspace, stream rings, tables) is taken from dev_alloc(bytes, alloc_ctx) and handed back
+     with dev_free(ptr, alloc_ctx) instead of hipMalloc / hipFree, e.g. to share a framework's
+     caching allocator.  Returned memory must be device memory of `device`, 256-byte aligned;
+     NULL means out of memory (MF_EDEVICE).  Calls may come from the engine's scheduler thread. */
+  void* (*dev_alloc)(size_t bytes, void* ctx);
+  void (*dev_free)(void* ptr, void* ctx);
+  void* alloc_ctx;
 } mf_runtime_cfg;
 
 typedef struct mf_stream_cfg {

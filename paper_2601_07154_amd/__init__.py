@@ -46,18 +46,51 @@ def rows_per_frame(height: int, width: int) -> int:
     return _lib.lib().mf_rows_per_frame(height, width)
 
 
+class _TorchAllocator:
+    """Device buffers for the engine from torch's caching allocator (uint8 tensors kept alive by
+    address until the engine hands them back)."""
+
+    def __init__(self, device: int):
+        import threading
+
+        import torch
+        self.torch, self.device, self.live, self.lock = torch, device, {}, threading.Lock()
+        self.c_alloc = _lib.DEV_ALLOC(self._alloc)
+        self.c_free = _lib.DEV_FREE(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            t = self.torch.empty(max(int(nbytes), 1), dtype=self.torch.uint8, device=f"cuda:{self.device}")
+        except RuntimeError:
+            return None
+        with self.lock:
+            self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, ctx):
+        with self.lock:
+            self.live.pop(ptr, None)
+
+
 class Engine:
     """mf_engine: weights on the device, batch workspace, optional scheduler thread."""
 
     def __init__(self, depth: int, dim: int, heads: int, mlp: int, weights: np.ndarray,
                  precision: str = "bf16", threaded: bool = False, max_tokens: int = 0,
                  hbm_budget: int = 0, device: int = 0, stream: int | None = None, graphs: bool = True,
-                 lib=None):
+                 allocator: str | None = None, lib=None):
+        """allocator="torch": the engine's device memory comes from torch's caching allocator."""
         self.lib = lib or _lib.lib()
         w = np.ascontiguousarray(weights, dtype=np.float32)
         m = _lib.ModelCfg(depth, dim, heads, mlp, 14, PRECISIONS[precision])
         rt = _lib.RuntimeCfg(device, 1 if threaded else 0, max_tokens, hbm_budget,
                              C.c_void_p(stream) if stream else None, 1 if graphs else 0, 0)
+        self._alloc = None
+        if allocator == "torch":
+            self._alloc = _TorchAllocator(device)
+            rt.dev_alloc, rt.dev_free = self._alloc.c_alloc, self._alloc.c_free
+        elif allocator is not None:
+            raise ValueError(f"unknown allocator {allocator!r}")
         h = C.c_void_p()
         _check(self.lib.mf_engine_create(C.byref(m), C.c_void_p(w.ctypes.data), w.size, C.byref(rt),
                                          C.byref(h)), "mf_engine_create", lib=self.lib)

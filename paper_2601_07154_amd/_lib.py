@@ -24,10 +24,15 @@ class ModelCfg(C.Structure):
                 ("patch", C.c_int32), ("precision", C.c_int32)]
 
 
+DEV_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class RuntimeCfg(C.Structure):
     _fields_ = [("device", C.c_int32), ("threaded", C.c_int32), ("max_tokens_per_batch", C.c_int64),
                 ("hbm_budget_bytes", C.c_uint64), ("stream", C.c_void_p), ("use_graphs", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("dev_alloc", DEV_ALLOC), ("dev_free", DEV_FREE),
+                ("alloc_ctx", C.c_void_p)]
 
 
 class StreamCfg(C.Structure):

@@ -67,6 +67,10 @@ class HipExecutor : public Executor {
     qt_ = attention_q_tile(dt_, hd_);
     const size_t want = expected_floats();
     if (n != want) { err = "weight blob has " + std::to_string(n) + " floats, the model needs " + std::to_string(want); return MF_EINVAL; }
+    if (!rt.dev_alloc != !rt.dev_free) { err = "dev_alloc and dev_free go together"; return MF_EINVAL; }
+    ualloc_ = rt.dev_alloc;
+    ufree_ = rt.dev_free;
+    uctx_ = rt.alloc_ctx;
     HIPCHECK(hipSetDevice(rt.device));
     device_ = rt.device;
     use_graphs_ = rt.use_graphs != 0;
@@ -107,9 +111,9 @@ class HipExecutor : public Executor {
   mf_status open_stream(const mf_stream_cfg& c, StreamRes* r, std::string& err) override {
     HIPCHECK(hipSetDevice(device_));
     const uint64_t hw = (uint64_t)c.height * c.width;
-    HIPCHECK(hipMalloc(&r->ring, (size_t)r->ring_cap * 3 * hw * 4));
-    if (r->map_cap > 0) HIPCHECK(hipMalloc(&r->maps, (size_t)r->map_cap * hw * 4));
-    HIPCHECK(hipMalloc(&r->hist, (size_t)r->hist_n * sizeof(FrameHist)));
+    HIPCHECK(dmalloc(&r->ring, (size_t)r->ring_cap * 3 * hw * 4));
+    if (r->map_cap > 0) HIPCHECK(dmalloc(&r->maps, (size_t)r->map_cap * hw * 4));
+    HIPCHECK(dmalloc(&r->hist, (size_t)r->hist_n * sizeof(FrameHist)));
     HIPCHECK(hipMemsetAsync(r->hist, 0, (size_t)r->hist_n * sizeof(FrameHist), copy_));
     HIPCHECK(hipMemsetAsync(r->ring, 0, (size_t)r->ring_cap * 3 * hw * 4, copy_));
     HIPCHECK(hipStreamSynchronize(copy_));
@@ -118,9 +122,9 @@ class HipExecutor : public Executor {
 
   void close_stream(StreamRes* r) override {
     hipSetDevice(device_);
-    if (r->ring) hipFree(r->ring);
-    if (r->maps) hipFree(r->maps);
-    if (r->hist) hipFree(r->hist);
+    dfree(r->ring);
+    dfree(r->maps);
+    dfree(r->hist);
     r->ring = r->maps = r->hist = nullptr;
   }
 
@@ -417,20 +421,20 @@ class HipExecutor : public Executor {
 
   // ------------------------------------------------------------------ weights
   mf_status load_weights(const float* w, size_t n, std::string& err) {
-    HIPCHECK(hipMalloc(&wdev_, n * 4));
+    HIPCHECK(dmalloc(&wdev_, n * 4));
     HIPCHECK(hipMemcpy(wdev_, w, n * 4, hipMemcpyHostToDevice));
     const float* p = wdev_;
     auto take = [&](size_t cnt) { const float* q = p; p += cnt; return q; };
     const size_t D = D_, F = F_;
     const float* Wp = take(588 * D);
     b_p_ = take(D); c_ref_ = take(D); c_other_ = take(D);
-    HIPCHECK(hipMalloc(&Wp_, D * KP * es_));
+    HIPCHECK(dmalloc(&Wp_, D * KP * es_));
     HIPCHECK(hipMemsetAsync(Wp_, 0, D * KP * es_, st_));
     HIPCHECK(convert_transpose(dt_, Wp, 588, (int)D, Wp_, KP, st_));
     layers_.resize(depth_);
     if (fp8_) {
-      HIPCHECK(hipMalloc(&wscale_, (size_t)depth_ * 3 * sizeof(float)));
-      HIPCHECK(hipMalloc(&wamax_, 64));
+      HIPCHECK(dmalloc(&wscale_, (size_t)depth_ * 3 * sizeof(float)));
+      HIPCHECK(dmalloc(&wamax_, 64));
     }
     for (int l = 0; l < depth_; ++l) {
       LayerW& L = layers_[l];
@@ -445,10 +449,10 @@ class HipExecutor : public Executor {
       const float* W2 = take(F * D);
       L.b_2 = take(D);
       const size_t ws = fp8_ ? 1 : es_;
-      HIPCHECK(hipMalloc(&L.Wqkv, 3 * D * D * ws));
-      HIPCHECK(hipMalloc(&L.Wo, D * D * es_));
-      HIPCHECK(hipMalloc(&L.W1, D * F * ws));
-      HIPCHECK(hipMalloc(&L.W2, F * D * ws));
+      HIPCHECK(dmalloc(&L.Wqkv, 3 * D * D * ws));
+      HIPCHECK(dmalloc(&L.Wo, D * D * es_));
+      HIPCHECK(dmalloc(&L.W1, D * F * ws));
+      HIPCHECK(dmalloc(&L.W2, F * D * ws));
       if (fp8_) {
         float* sc = wscale_ + 3 * l;
         HIPCHECK(quantize_weight_fp8(Wqkv, (int)D, (int)(3 * D), (unsigned char*)L.Wqkv, (int)D, wamax_, sc, st_));
@@ -467,7 +471,7 @@ class HipExecutor : public Executor {
     h_1_ = take(D);
     H_2_ = take(D * 9);
     h_2_ = take(9);
-    HIPCHECK(hipMalloc(&H1t_, D * D * 4));
+    HIPCHECK(dmalloc(&H1t_, D * D * 4));
     HIPCHECK(convert_transpose(DT_F32, H1, (int)D, (int)D, H1t_, (int)D, st_));
     HIPCHECK(hipStreamSynchronize(st_));
     return MF_OK;
@@ -475,14 +479,14 @@ class HipExecutor : public Executor {
 
   mf_status alloc_workspace(std::string& err) {
     const size_t D = D_, wide = std::max<int64_t>(F_, KP);
-    HIPCHECK(hipMalloc(&X_, (size_t)mcap_ * D * 4));
-    HIPCHECK(hipMalloc(&Y_, (size_t)mcap_ * D * es_));
-    HIPCHECK(hipMalloc(&O_, (size_t)mcap_ * D * es_));
-    HIPCHECK(hipMalloc(&Hb_, (size_t)mcap_ * wide * es_));
-    HIPCHECK(hipMalloc(&rowinfo_, (size_t)mcap_ * 4));
-    HIPCHECK(hipMalloc(&Q_, (size_t)mpad_ * D * es_));
-    HIPCHECK(hipMalloc(&K_, (size_t)mpad_ * D * es_));
-    HIPCHECK(hipMalloc(&Vt_, (size_t)mpad_ * D * es_));
+    HIPCHECK(dmalloc(&X_, (size_t)mcap_ * D * 4));
+    HIPCHECK(dmalloc(&Y_, (size_t)mcap_ * D * es_));
+    HIPCHECK(dmalloc(&O_, (size_t)mcap_ * D * es_));
+    HIPCHECK(dmalloc(&Hb_, (size_t)mcap_ * wide * es_));
+    HIPCHECK(dmalloc(&rowinfo_, (size_t)mcap_ * 4));
+    HIPCHECK(dmalloc(&Q_, (size_t)mpad_ * D * es_));
+    HIPCHECK(dmalloc(&K_, (size_t)mpad_ * D * es_));
+    HIPCHECK(dmalloc(&Vt_, (size_t)mpad_ * D * es_));
     // rows past the last token are read (masked) by attention tiles: keep them finite
     HIPCHECK(hipMemsetAsync(Q_, 0, (size_t)mpad_ * D * es_, st_));
     HIPCHECK(hipMemsetAsync(K_, 0, (size_t)mpad_ * D * es_, st_));
@@ -492,18 +496,18 @@ class HipExecutor : public Executor {
     HIPCHECK(hipMemsetAsync(O_, 0, (size_t)mcap_ * D * es_, st_));
     HIPCHECK(hipStreamSynchronize(st_));
     if (fp8_) {
-      HIPCHECK(hipMalloc(&Y8_, (size_t)mcap_ * D));
-      HIPCHECK(hipMalloc(&H8_, (size_t)mcap_ * F_));
-      HIPCHECK(hipMalloc(&srow_, (size_t)mcap_ * 4));
-      HIPCHECK(hipMalloc(&srow2_, (size_t)mcap_ * 4));
-      HIPCHECK(hipMalloc(&amax_, (size_t)fcap_ * 4));
+      HIPCHECK(dmalloc(&Y8_, (size_t)mcap_ * D));
+      HIPCHECK(dmalloc(&H8_, (size_t)mcap_ * F_));
+      HIPCHECK(dmalloc(&srow_, (size_t)mcap_ * 4));
+      HIPCHECK(dmalloc(&srow2_, (size_t)mcap_ * 4));
+      HIPCHECK(dmalloc(&amax_, (size_t)fcap_ * 4));
     }
-    HIPCHECK(hipMalloc(&camln_, (size_t)fcap_ * D * 4));
-    HIPCHECK(hipMalloc(&camg_, (size_t)fcap_ * D * 4));
-    HIPCHECK(hipMalloc(&pose9_, (size_t)fcap_ * 9 * 4));
-    HIPCHECK(hipMalloc(&tloc_, (size_t)fcap_ * 16 * 8));
-    HIPCHECK(hipMalloc(&res_, (size_t)fcap_ * sizeof(mf_focus)));
-    HIPCHECK(hipMalloc(&keys_, (size_t)fcap_ * 8));
+    HIPCHECK(dmalloc(&camln_, (size_t)fcap_ * D * 4));
+    HIPCHECK(dmalloc(&camg_, (size_t)fcap_ * D * 4));
+    HIPCHECK(dmalloc(&pose9_, (size_t)fcap_ * 9 * 4));
+    HIPCHECK(dmalloc(&tloc_, (size_t)fcap_ * 16 * 8));
+    HIPCHECK(dmalloc(&res_, (size_t)fcap_ * sizeof(mf_focus)));
+    HIPCHECK(dmalloc(&keys_, (size_t)fcap_ * 8));
     HIPCHECK(hipHostMalloc((void**)&res_host_, (size_t)fcap_ * sizeof(mf_focus), hipHostMallocDefault));
     return MF_OK;
   }
@@ -522,10 +526,11 @@ class HipExecutor : public Executor {
   mf_status ensure_tables(size_t bytes, std::string& err) {
     if (bytes <= tab_cap_) return MF_OK;
     clear_graphs();   // captured copies point at the old table buffers
-    if (tab_dev_) HIPCHECK(hipFree(tab_dev_));
+    dfree(tab_dev_);
+    tab_dev_ = nullptr;
     if (tab_host_) HIPCHECK(hipHostFree(tab_host_));
     tab_cap_ = align_up(bytes * 2, 1 << 20);
-    HIPCHECK(hipMalloc((void**)&tab_dev_, tab_cap_));
+    HIPCHECK(dmalloc(&tab_dev_, tab_cap_));
     HIPCHECK(hipHostMalloc((void**)&tab_host_, tab_cap_, hipHostMallocDefault));
     return MF_OK;
   }
@@ -537,7 +542,7 @@ class HipExecutor : public Executor {
     if (it != pe_index_.end()) { *base = it->second; return MF_OK; }
     if (!pe_) {
       pe_cap_ = 32768;
-      HIPCHECK(hipMalloc(&pe_, (size_t)pe_cap_ * D_ * 4));
+      HIPCHECK(dmalloc(&pe_, (size_t)pe_cap_ * D_ * 4));
     }
     if (pe_rows_ + gh * gw > pe_cap_) { err = "too many distinct resolutions for the position-code arena"; return MF_ENOMEM; }
     HIPCHECK(make_pe(pe_ + (size_t)pe_rows_ * D_, gh, gw, D_, copy_));
@@ -711,7 +716,7 @@ class HipExecutor : public Executor {
   void release() {
     hipSetDevice(device_);
     clear_graphs();
-    auto F = [](void* p) { if (p) hipFree(p); };
+    auto F = [this](void* p) { dfree(p); };
     F(wdev_); F(Wp_); F(H1t_);
     for (auto& L : layers_) { F(L.Wqkv); F(L.Wo); F(L.W1); F(L.W2); }
     F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(Q_); F(K_); F(Vt_);
@@ -725,6 +730,29 @@ class HipExecutor : public Executor {
     if (copy_) hipStreamDestroy(copy_);
     if (own_stream_ && st_) hipStreamDestroy(st_);
   }
+
+  // device memory: the caller's allocator when one was given, else hipMalloc
+  template <typename T>
+  hipError_t dmalloc(T** p, size_t bytes) {
+    if (!ualloc_) return hipMalloc((void**)p, bytes);
+    *p = (T*)ualloc_(bytes, uctx_);
+    if (!*p && bytes) return hipErrorOutOfMemory;
+    if (((uintptr_t)*p & 255) != 0) return hipErrorInvalidValue;
+    return hipSuccess;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    if (ufree_) {
+      // hipFree waits for the device; the caller's allocator may hand the memory out again at once
+      hipDeviceSynchronize();
+      ufree_(p, uctx_);
+    } else {
+      hipFree(p);
+    }
+  }
+  void* (*ualloc_)(size_t, void*) = nullptr;
+  void (*ufree_)(void*, void*) = nullptr;
+  void* uctx_ = nullptr;
 
   mf_model_cfg m_{};
   int D_ = 0, H_ = 0, hd_ = 0, F_ = 0, depth_ = 0, device_ = 0, qt_ = 128;

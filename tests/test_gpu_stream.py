@@ -171,3 +171,40 @@ def test_graph_replays_match_eager():
         m.op_layernorm("fp32", x, y, torch.ones(384, device="cuda"), torch.zeros(384, device="cuda"))
         torch.cuda.synchronize()
     eng.close()
+
+
+@pytest.mark.parametrize("threaded", [False, True])
+def test_torch_allocator_matches_default(threaded):
+    """With allocator="torch" every device buffer of the engine comes from torch's caching
+    allocator (through the C ABI's dev_alloc / dev_free); the results are bitwise those of the
+    engine's own hipMalloc path, and closing the engine hands every buffer back."""
+    torch = torch_cuda()
+    m = mf()
+    wl = mf_synth.TINY
+    blob = mf_synth.make_weights(wl.model, wl.seed_weights)
+    frames = torch.from_numpy(mf_synth.workload_frames(wl)).cuda()
+    K = (wl.fx, wl.fy, wl.cx, wl.cy)
+
+    def run(alloc):
+        eng = m.Engine.from_model(wl.model, blob, precision="bf16", max_tokens=4096, threaded=threaded,
+                                  allocator=alloc)
+        held = len(eng._alloc.live) if alloc else 0
+        sid = eng.open_stream(wl.height, wl.width, wl.window, wl.overlap, K, sigma=50.0)
+        eng.push_frames(sid, frames, eos=True)
+        eng.sync()
+        recs, maps = _drain(eng, sid, wl.height, wl.width)
+        a = eng._alloc
+        eng.close()
+        return recs, maps, held, a
+
+    torch.cuda.synchronize()
+    base_mem = torch.cuda.memory_allocated()
+    r0, m0, _, _ = run(None)
+    r1, m1, held, alloc = run("torch")
+    assert held > 10                                   # weights and workspace came from torch
+    assert len(alloc.live) == 0                        # ... and all went back on close
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base_mem
+    for f in ("frame", "T_w2c", "pose9", "a_world", "u", "v", "valid", "peak_x", "peak_y"):
+        np.testing.assert_array_equal(r0[f], r1[f], err_msg=f)
+    np.testing.assert_array_equal(m0, m1)
