@@ -15,7 +15,10 @@ Readings of points the paper leaves open (each is a project decision):
   * gravity is the world y axis (OpenCV camera axes, first camera upright); the
     yaw of the alignment is atan2(A[0,2], A[2,2]) of its rotation;
   * the alignment translation keeps the anchor's camera centre continuous;
-  * the difference step is one frame; frames 0 and 1 carry no focus;
+  * the difference step is one frame (a stride s >= 1 is an option); frames before
+    the first full difference (0 and 1 at stride 1) carry no focus; the first
+    difference of Eq. 2 alone gives the velocity-based projection the paper
+    contrasts its focus with (Sec. 2.3), as a second mode;
   * a focus is valid iff |a_w| > 1e-12 max(1, |p_t|) and |a_c,z| > 1e-6 |a_c|;
   * map points are the last N valid accelerations rotated by the current
     camera's rotation; spread clip(sigma*s_i, sigma_min, sigma_max) pixels with
@@ -126,13 +129,26 @@ def project(a_c: np.ndarray, fx: float, fy: float, cx: float, cy: float):
     return cx + fx * a_c[0] / a_c[2], cy + fy * a_c[1] / a_c[2]
 
 
-def focus_track(T_w: np.ndarray, fx: float, fy: float, cx: float, cy: float):
+FOCUS_ACCEL = 0      # Eq. 3: second difference of the camera centres (the paper's focus)
+FOCUS_VELOCITY = 1   # Eq. 2: first difference, the velocity-based projection the paper contrasts
+
+
+def focus_track(T_w: np.ndarray, fx: float, fy: float, cx: float, cy: float, mode: int = FOCUS_ACCEL,
+                stride: int = 1):
     """Per-frame motion focus from world poses [N,4,4] (Eq. 1-6).
 
-    Returns a dict of arrays: p [N,3] camera centres, a_w [N,3] world acceleration,
-    a_c [N,3] camera-frame acceleration, uv [N,2], s [N] = |a_w|, valid [N] bool.
-    Frames 0 and 1 have no acceleration (valid = False, zeros).
+    The motion vector m_t is the acceleration a_w of Eq. 2-3 (mode FOCUS_ACCEL) or the velocity
+    v_t of Eq. 2 (mode FOCUS_VELOCITY), with the differences taken over `stride` frames:
+    a = p_t - 2 p_{t-s} + p_{t-2s}, v = p_t - p_{t-s} (stride 1 is the paper's).  It is rotated
+    into the camera (Eq. 4) and projected (Eq. 5-6) in either mode.
+
+    Returns a dict of arrays: p [N,3] camera centres, a_w [N,3] the world motion vector,
+    a_c [N,3] the camera-frame motion vector, uv [N,2], s [N] = |a_w|, valid [N] bool.
+    Frames before the first full difference (t < 2 stride, or t < stride for velocity) have no
+    motion vector (valid = False, zeros).
     """
+    if mode not in (FOCUS_ACCEL, FOCUS_VELOCITY) or stride < 1:
+        raise ValueError("mode must be FOCUS_ACCEL or FOCUS_VELOCITY and stride >= 1")
     N = T_w.shape[0]
     p = np.stack([camera_centre(T) for T in T_w]) if N else np.zeros((0, 3))
     a_w = np.zeros((N, 3))
@@ -140,11 +156,15 @@ def focus_track(T_w: np.ndarray, fx: float, fy: float, cx: float, cy: float):
     uv = np.zeros((N, 2))
     s = np.zeros(N)
     valid = np.zeros(N, dtype=bool)
-    for t in range(2, N):
-        v_t = p[t] - p[t - 1]
-        v_tm1 = p[t - 1] - p[t - 2]
-        a_w[t] = v_t - v_tm1                       # Eq. 2-3
-        a_c[t] = T_w[t, :3, :3] @ a_w[t]           # Eq. 4
+    first = stride if mode == FOCUS_VELOCITY else 2 * stride
+    for t in range(first, N):
+        v_t = p[t] - p[t - stride]                       # Eq. 2
+        if mode == FOCUS_VELOCITY:
+            a_w[t] = v_t
+        else:
+            v_tm1 = p[t - stride] - p[t - 2 * stride]
+            a_w[t] = v_t - v_tm1                         # Eq. 3
+        a_c[t] = T_w[t, :3, :3] @ a_w[t]                 # Eq. 4
         s[t] = np.linalg.norm(a_w[t])
         na_c = np.linalg.norm(a_c[t])
         ok = s[t] > 1e-12 * max(1.0, np.linalg.norm(p[t])) and abs(a_c[t, 2]) > 1e-6 * na_c

@@ -10,7 +10,8 @@ from . import motion, vit
 def run_stream(frames: np.ndarray, weights: dict, heads: int, window: int, overlap: int,
                K, n_points: int = 15, sigma: float = 1.0, sigma_min: float = 0.5,
                sigma_max: float | None = None, anchor_mode: int = motion.ANCHOR_YAW,
-               precision: str = "fp64", windows=None, maps: bool = True, patch: int = 14):
+               precision: str = "fp64", windows=None, maps: bool = True, patch: int = 14,
+               focus_mode: int = motion.FOCUS_ACCEL, stride: int = 1):
     """Run the oracle on one stream of frames [N,3,H,W].
 
     windows: optionally restrict to the first `windows` windows (large configs).
@@ -30,7 +31,7 @@ def run_stream(frames: np.ndarray, weights: dict, heads: int, window: int, overl
         p9s.append(p9)
         Tls.append(np.stack([vit.pose9_to_T(r) for r in p9]))
     T_w = motion.chain_windows(sched, Tls, anchor_mode)
-    track = motion.focus_track(T_w, fx, fy, cx, cy)
+    track = motion.focus_track(T_w, fx, fy, cx, cy, focus_mode, stride)
     out = dict(schedule=sched, pose9=p9s, T_loc=Tls, T_w=T_w, track=track)
     if maps:
         Ms, Zs, am = [], [], []
@@ -48,12 +49,12 @@ def run_stream(frames: np.ndarray, weights: dict, heads: int, window: int, overl
 
 def run_poses(T_w2c: np.ndarray, K, height: int, width: int, n_points: int = 15,
               sigma: float = 1.0, sigma_min: float = 0.5, sigma_max: float | None = None,
-              maps: bool = True):
+              maps: bool = True, focus_mode: int = motion.FOCUS_ACCEL, stride: int = 1):
     """Focus and maps for world poses given directly (the 'any pose estimator' entry)."""
     fx, fy, cx, cy = K
     if sigma_max is None:
         sigma_max = 4.0 * max(height, width)
-    track = motion.focus_track(T_w2c, fx, fy, cx, cy)
+    track = motion.focus_track(T_w2c, fx, fy, cx, cy, focus_mode, stride)
     out = dict(T_w=T_w2c, track=track)
     if maps:
         Ms, Zs, am = [], [], []

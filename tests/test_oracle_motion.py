@@ -167,6 +167,62 @@ def test_sway_path_of_the_workload_has_zero_acceleration():
     assert np.abs(tr["a_w"]).max() < 1e-13 and not tr["valid"].any()
 
 
+@pytest.mark.parametrize("stride", [1, 2, 5])
+def test_strided_acceleration_closed_form(stride):
+    """A quadratic path's second difference over s frames is exactly a (s dt)^2: the focus is the
+    stride-1 focus, and the first 2 s frames have none."""
+    fps, acc = 30.0, (0.1, -0.05, 0.5)
+    path = mf_synth.CameraPath(fps=fps, velocity=(0.2, 0.0, 1.5), accel=acc, sway_deg=0.0)
+    tr = motion.focus_track(path.poses(24), *K, mode=motion.FOCUS_ACCEL, stride=stride)
+    f = 2 * stride
+    np.testing.assert_allclose(tr["a_w"][f:], np.tile(np.array(acc) * (stride / fps) ** 2, (24 - f, 1)),
+                               rtol=1e-9, atol=1e-15)
+    fx, fy, cx, cy = K
+    np.testing.assert_allclose(tr["uv"][f:, 0], cx + fx * 0.1 / 0.5, rtol=1e-9)
+    assert not tr["valid"][:f].any() and tr["valid"][f:].all() and not tr["a_w"][:f].any()
+
+
+@pytest.mark.parametrize("stride", [1, 3])
+def test_velocity_mode_is_the_focus_of_expansion(stride):
+    """Velocity mode on a straight constant-velocity path: m = v s dt exactly, and the point is
+    the focus of expansion, the projection of the direction of travel: the principal point for
+    motion along the optical axis; cx - fx tan(psi) with the head turned by psi."""
+    fx, fy, cx, cy = K
+    fwd = mf_synth.CameraPath(velocity=(0, 0, 1.5), accel=(0, 0, 0), sway_deg=0.0)
+    tr = motion.focus_track(fwd.poses(12), *K, mode=motion.FOCUS_VELOCITY, stride=stride)
+    np.testing.assert_allclose(tr["a_w"][stride:], np.tile([0, 0, 1.5 * stride / 30.0], (12 - stride, 1)),
+                               atol=1e-12)
+    np.testing.assert_allclose(tr["uv"][stride:], np.tile([cx, cy], (12 - stride, 1)), atol=1e-9)
+    assert not tr["valid"][:stride].any() and tr["valid"][stride:].all()
+    psi = 17.0
+    turned = mf_synth.CameraPath(velocity=(0, 0, 1.0), accel=(0, 0, 0), sway_deg=0.0, yaw0_deg=psi)
+    tr = motion.focus_track(turned.poses(10), *K, mode=motion.FOCUS_VELOCITY, stride=stride)
+    np.testing.assert_allclose(tr["uv"][stride:, 0], cx - fx * math.tan(math.radians(psi)), rtol=1e-9)
+
+
+def test_velocity_and_acceleration_differ_when_turning():
+    """Braking while moving forward and sideways: velocity mode points along the travel direction,
+    acceleration mode along the (opposite, braking) acceleration, on the other side of the image."""
+    fx, fy, cx, cy = K
+    path = mf_synth.CameraPath(velocity=(0.5, 0, 1.5), accel=(-0.6, 0, 0.4), sway_deg=0.0)
+    T = path.poses(6)
+    vel = motion.focus_track(T, *K, mode=motion.FOCUS_VELOCITY)
+    acc = motion.focus_track(T, *K, mode=motion.FOCUS_ACCEL)
+    t = 5
+    p = [motion.camera_centre(T[i]) for i in range(6)]
+    np.testing.assert_allclose(vel["a_w"][t], p[t] - p[t - 1], atol=1e-15)
+    np.testing.assert_allclose(acc["a_w"][t], p[t] - 2 * p[t - 1] + p[t - 2], atol=1e-15)
+    assert vel["uv"][t, 0] > cx > acc["uv"][t, 0]
+
+
+def test_focus_track_rejects_bad_mode_and_stride():
+    T = mf_synth.CameraPath().poses(4)
+    with pytest.raises(ValueError):
+        motion.focus_track(T, *K, mode=2)
+    with pytest.raises(ValueError):
+        motion.focus_track(T, *K, stride=0)
+
+
 # ----------------------------------------------------------------------------- map
 def test_single_point_map():
     H, W, u, v, sig = 40, 60, 23.0, 17.0, 4.0
