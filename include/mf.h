@@ -48,6 +48,11 @@ typedef int32_t mf_status;
 #define MF_ANCHOR_YAW 0 /* lock pitch and roll, propagate yaw and translation (the paper) */
 #define MF_ANCHOR_SE3 1 /* full rigid alignment (no lock) */
 
+/* Motion vector of the focus (Sec. 2.3), differences over s = diff_stride frames: */
+#define MF_FOCUS_ACCEL 0    /* a_w = p_t - 2 p_{t-s} + p_{t-2s} (Eq. 3 at s = 1; the paper's focus) */
+#define MF_FOCUS_VELOCITY 1 /* v = p_t - p_{t-s} (Eq. 2): the velocity-based projection the paper
+                               contrasts with (focus of expansion) */
+
 /* push flags */
 #define MF_EOS 1          /* these are the stream's last frames */
 #define MF_DEVICE_PTR 2   /* the pointer is device memory (HIP) */
@@ -94,11 +99,14 @@ typedef struct mf_stream_cfg {
   int32_t emit_maps;            /* 1: render the focus map of every emitted frame */
   int32_t ring_frames;          /* device frame ring capacity (0: 2L + 8) */
   int32_t result_frames;        /* results (and maps) held until polled (0: 4L) */
+  int32_t focus_mode;           /* MF_FOCUS_ACCEL (Eq. 3, the paper's) or MF_FOCUS_VELOCITY (Eq. 2) */
+  int32_t diff_stride;          /* frames between the differenced centres, 1..64 (0: 1, the paper's) */
   int32_t reserved;
 } mf_stream_cfg;
 
-/* One emitted frame.  valid bit 0: focus point defined (t >= 2, |a_w| > 0, a_z not ~0);
-   bit 1: the map is non-zero. */
+/* One emitted frame.  valid bit 0: focus point defined (t >= 2 s, or t >= s for velocity;
+   |a_w| > 0; a_z not ~0); bit 1: the map is non-zero.  a_world / a_cam / s hold the motion
+   vector of the stream's focus mode (the velocity in MF_FOCUS_VELOCITY). */
 typedef struct mf_focus {
   int64_t frame;            /* frame index within the stream */
   int32_t window;           /* window that emitted it */

@@ -124,10 +124,12 @@ class Engine:
     def open_stream(self, height: int, width: int, window: int, overlap: int, K, n_points: int = 15,
                     sigma: float = 1.0, sigma_min: float = 0.0, sigma_max: float = 0.0,
                     anchor_mode: int = MF_ANCHOR_YAW, emit_maps: bool = True, ring_frames: int = 0,
-                    result_frames: int = 0, allow_again: bool = False) -> int:
+                    result_frames: int = 0, allow_again: bool = False, focus_mode: int = 0,
+                    diff_stride: int = 1) -> int:
         fx, fy, cx, cy = K
         c = _lib.StreamCfg(height, width, window, overlap, fx, fy, cx, cy, n_points, anchor_mode, sigma,
-                           sigma_min, sigma_max, 1 if emit_maps else 0, ring_frames, result_frames, 0)
+                           sigma_min, sigma_max, 1 if emit_maps else 0, ring_frames, result_frames, focus_mode,
+                           diff_stride, 0)
         sid = C.c_int32()
         st = self.lib.mf_open_stream(self.h, C.byref(c), C.byref(sid))
         if allow_again and st == MF_EAGAIN:

@@ -41,7 +41,7 @@ class StreamCfg(C.Structure):
                 ("n_points", C.c_int32), ("anchor_mode", C.c_int32),
                 ("sigma", C.c_double), ("sigma_min", C.c_double), ("sigma_max", C.c_double),
                 ("emit_maps", C.c_int32), ("ring_frames", C.c_int32), ("result_frames", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("focus_mode", C.c_int32), ("diff_stride", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Focus(C.Structure):

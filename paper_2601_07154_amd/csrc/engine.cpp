@@ -87,6 +87,10 @@ struct Engine {
   }
 };
 
+// Frames of history the device looks back on beyond those a batch emits: the N map points, the
+// anchor inside the window, and the 2 s frames of the centre differences.
+static int hist_lookback(const mf_stream_cfg& c) { return c.n_points + c.window + 8 + 2 * c.diff_stride; }
+
 // ------------------------------------------------------------------ schedule
 // The next window of a frame stream if all its frames are here (not committed).
 static bool peek_window(const Stream& s, BatchWindow& w) {
@@ -172,7 +176,7 @@ static int step(Engine& e) {
       if (s.released) continue;
       // frames one stream may emit in a batch: its device history must still hold the
       // accelerations the maps of the oldest of them read
-      const int64_t span = s.res.hist_n - s.cfg.n_points - s.cfg.window - 8;
+      const int64_t span = s.res.hist_n - hist_lookback(s.cfg);
       int64_t emitted_here = 0;
       if (s.kind == 1) {
         const int64_t rows = e.ex->rows_per_frame(s.cfg.height, s.cfg.width);
@@ -413,6 +417,15 @@ mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream
     set_err("unknown anchor mode %d", c.anchor_mode);
     return MF_EINVAL;
   }
+  if (c.focus_mode != MF_FOCUS_ACCEL && c.focus_mode != MF_FOCUS_VELOCITY) {
+    set_err("unknown focus mode %d", c.focus_mode);
+    return MF_EINVAL;
+  }
+  if (c.diff_stride == 0) c.diff_stride = 1;
+  if (c.diff_stride < 1 || c.diff_stride > 64) {
+    set_err("diff_stride must be in 1..64");
+    return MF_EINVAL;
+  }
   if (!(c.fx != 0.0) || !(c.fy != 0.0)) {
     set_err("focal lengths must be non-zero");
     return MF_EINVAL;
@@ -440,9 +453,9 @@ mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream
     return MF_EINVAL;
   }
   // history ring: the frames one batch may emit for this stream (at least 8 windows' worth),
-  // plus the N points and the window that the maps and the anchor look back on
+  // plus what the maps, the anchor and the differences look back on
   int hist_n = 64;
-  while (hist_n < std::max(8 * c.window, 256) + c.n_points + c.window + 8) hist_n *= 2;
+  while (hist_n < std::max(8 * c.window, 256) + hist_lookback(c)) hist_n *= 2;
   const uint64_t need = e->ex->stream_bytes(c, c.ring_frames, c.emit_maps ? c.result_frames : 0, hist_n);
   auto s = std::make_shared<Stream>();
   {
@@ -602,7 +615,7 @@ mf_status mf_push_poses(mf_engine* e, int32_t stream_id, const double* T, int32_
         set_err("world poses must continue the stream at frame %lld", (long long)s->emitted_end);
         return MF_EINVAL;
       }
-      const int span = s->res.hist_n - s->cfg.n_points - s->cfg.window - 8;
+      const int span = s->res.hist_n - hist_lookback(s->cfg);
       if (n > span) {
         set_err("push at most %d world poses per call", span);
         return MF_EINVAL;

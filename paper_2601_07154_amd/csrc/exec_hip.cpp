@@ -192,6 +192,8 @@ class HipExecutor : public Executor {
         sd.fx = w.cfg->fx; sd.fy = w.cfg->fy; sd.cx = w.cfg->cx; sd.cy = w.cfg->cy;
         sd.sigma = w.cfg->sigma; sd.sigma_min = w.cfg->sigma_min; sd.sigma_max = w.cfg->sigma_max;
         sd.anchor_mode = w.cfg->anchor_mode;
+        sd.focus_mode = w.cfg->focus_mode;
+        sd.stride = w.cfg->diff_stride > 0 ? w.cfg->diff_stride : 1;
         sd.H = w.cfg->height; sd.W = w.cfg->width;
         sd.map_cap = w.res->map_cap;
         sd.maps = (float*)w.res->maps;

@@ -81,7 +81,7 @@ namespace mf {
 
 struct FrameHist {            // per-stream device history entry (ring indexed by frame & mask)
   double T[16];               // world-to-camera pose
-  double a_w[3];              // world acceleration (Eq. 3)
+  double a_w[3];              // world motion vector (acceleration, Eq. 3, or velocity, Eq. 2)
   double s;                   // |a_w|
   int32_t valid;              // focus point defined
   int32_t pad;
@@ -92,6 +92,7 @@ struct StreamDev {            // per-stream constants of one batch
   double fx, fy, cx, cy, sigma, sigma_min, sigma_max;
   int32_t anchor_mode, H, W, map_cap;
   float* maps;                // map ring [map_cap][H][W]
+  int32_t focus_mode, stride; // MF_FOCUS_ACCEL / MF_FOCUS_VELOCITY, difference stride s
 };
 
 enum ChainMode { CHAIN_ANCHOR = 0, CHAIN_FIRST = 1, CHAIN_WORLD = 2 };

@@ -4,7 +4,8 @@
 // (window k's anchor needs window k-1's world pose).  For each window: the alignment A from
 // the anchor frame (the last frame the previous window emitted, shared by both windows);
 // world poses T_w(t) = T_loc(t) A of the new frames; then per new frame the camera centre
-// p_t = -R_t^T t_t, a_w = p_t - 2 p_{t-1} + p_{t-2}, a_c = R_t a_w and the pinhole focus.
+// p_t = -R_t^T t_t, a_w = p_t - 2 p_{t-s} + p_{t-2s} (or v = p_t - p_{t-s} in velocity mode),
+// a_c = R_t a_w and the pinhole focus.
 //
 // focus_maps: per emitted frame, the last N valid accelerations rotated by the frame's
 // rotation and projected are the Gaussian centres; spread clip(sigma |a_w,i|); the map is
@@ -108,12 +109,14 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
       r.reserved = 0.0f;
       double aw[3] = {0.0, 0.0, 0.0}, ac[3] = {0.0, 0.0, 0.0}, u = 0.0, v = 0.0, s = 0.0;
       int valid = 0;
-      if (t >= 2) {
-        double p0[3], p1[3], p2[3];
+      const int ds = sd.stride;
+      const bool velocity = sd.focus_mode == MF_FOCUS_VELOCITY;
+      if (t >= (velocity ? ds : 2 * ds)) {
+        double p0[3], p1[3], p2[3] = {0.0, 0.0, 0.0};
         centre(h.T, p0);
-        centre(hist[(t - 1) & mask].T, p1);
-        centre(hist[(t - 2) & mask].T, p2);
-        for (int i = 0; i < 3; ++i) aw[i] = (p0[i] - p1[i]) - (p1[i] - p2[i]);
+        centre(hist[(t - ds) & mask].T, p1);
+        if (!velocity) centre(hist[(t - 2 * ds) & mask].T, p2);
+        for (int i = 0; i < 3; ++i) aw[i] = velocity ? p0[i] - p1[i] : (p0[i] - p1[i]) - (p1[i] - p2[i]);
         for (int i = 0; i < 3; ++i) ac[i] = h.T[i * 4 + 0] * aw[0] + h.T[i * 4 + 1] * aw[1] + h.T[i * 4 + 2] * aw[2];
         s = sqrt(aw[0] * aw[0] + aw[1] * aw[1] + aw[2] * aw[2]);
         const double np = sqrt(p0[0] * p0[0] + p0[1] * p0[1] + p0[2] * p0[2]);

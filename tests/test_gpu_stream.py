@@ -25,11 +25,12 @@ def _drain(eng, sid, H, W, cap=4096):
     return np.concatenate(recs), np.concatenate(maps)
 
 
-def _run_poses_engine(m, T, K, H, W, sigma, n_points=15, local_windows=None):
+def _run_poses_engine(m, T, K, H, W, sigma, n_points=15, local_windows=None, focus_mode=0, diff_stride=1):
     eng = m.Engine(1, 128, 4, 128, np.zeros(mf_synth.weight_count(mf_synth.ModelConfig(1, 128, 4, 128)),
                                             np.float32), precision="fp32", max_tokens=16384)
     n = len(T) if T is not None else sum(len(t) for _, t in local_windows)
-    sid = eng.open_stream(H, W, 16, 8, K, n_points=n_points, sigma=sigma, result_frames=max(64, n))
+    sid = eng.open_stream(H, W, 16, 8, K, n_points=n_points, sigma=sigma, result_frames=max(64, n),
+                          focus_mode=focus_mode, diff_stride=diff_stride)
     if local_windows is None:
         eng.push_poses(sid, T, 0, eos=True)
     else:
@@ -82,6 +83,31 @@ def test_world_poses_match_oracle_track_and_maps():
             assert ref["maps"][i].ravel()[am] >= 1.0 - 1e-5
         else:
             assert not (r["valid"] & 2) and not maps[i].any()
+
+
+@pytest.mark.parametrize("focus_mode,stride", [(0, 3), (1, 1), (1, 4)])
+def test_focus_modes_and_strides_match_oracle(focus_mode, stride):
+    """Velocity-based projection and strided differences: motion vectors, focus points, validity
+    and maps against the oracle (FP64 on both sides)."""
+    torch_cuda()
+    m = mf()
+    K = (400.0, 380.0, 252.0, 140.0)
+    H, W = 140, 252
+    path = mf_synth.CameraPath(velocity=(0.2, 0.0, 1.5), accel=(0.3, -0.1, 0.5), sway_deg=3.0)
+    T = path.poses(60)
+    sigma = 3e4 if focus_mode == 0 else 300.0
+    recs, maps = _run_poses_engine(m, T, K, H, W, sigma, focus_mode=focus_mode, diff_stride=stride)
+    ref = pipeline.run_poses(T, K, H, W, sigma=sigma, focus_mode=focus_mode, stride=stride)
+    tr = ref["track"]
+    first = stride if focus_mode == 1 else 2 * stride
+    assert not (recs["valid"][:first] & 1).any()
+    np.testing.assert_array_equal(recs["valid"] & 1, tr["valid"].astype(np.int32))
+    v = tr["valid"]
+    np.testing.assert_allclose(recs["a_world"], tr["a_w"], rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(recs["a_cam"], tr["a_c"], rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(recs["u"][v], tr["uv"][v, 0], rtol=1e-9)
+    np.testing.assert_allclose(recs["v"][v], tr["uv"][v, 1], rtol=1e-9)
+    np.testing.assert_allclose(maps, ref["maps"], atol=1e-5)
 
 
 def test_local_poses_anchoring_matches_oracle():

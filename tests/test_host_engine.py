@@ -174,14 +174,17 @@ def test_admission_by_hbm_budget(hostlib):
 
 
 @pytest.mark.parametrize("kw", [dict(height=30), dict(width=0), dict(overlap=0), dict(overlap=8), dict(n_points=0),
-                                dict(n_points=33), dict(anchor_mode=7), dict(fx=0.0)])
+                                dict(n_points=33), dict(anchor_mode=7), dict(fx=0.0), dict(focus_mode=2),
+                                dict(diff_stride=-1), dict(diff_stride=65)])
 def test_invalid_stream_configs(hostlib, kw):
     eng = engine(hostlib)
-    args = dict(height=28, width=28, window=8, overlap=4, fx=50.0, n_points=15, anchor_mode=0)
+    args = dict(height=28, width=28, window=8, overlap=4, fx=50.0, n_points=15, anchor_mode=0, focus_mode=0,
+                diff_stride=1)
     args.update(kw)
     with pytest.raises(mfp.MfError) as e:
         eng.open_stream(args["height"], args["width"], args["window"], args["overlap"], (args["fx"], 50, 14, 14),
-                        n_points=args["n_points"], anchor_mode=args["anchor_mode"])
+                        n_points=args["n_points"], anchor_mode=args["anchor_mode"], focus_mode=args["focus_mode"],
+                        diff_stride=args["diff_stride"])
     assert e.value.status == mfp._lib.MF_EINVAL
     eng.close()
 
