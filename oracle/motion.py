@@ -15,6 +15,9 @@ Readings of points the paper leaves open (each is a project decision):
   * gravity is the world y axis (OpenCV camera axes, first camera upright); the
     yaw of the alignment is atan2(A[0,2], A[2,2]) of its rotation;
   * the alignment translation keeps the anchor's camera centre continuous;
+  * an option rescales each window's translations first, by the ratio of its
+    shared frames' centre distances to the anchor in the world and in the window
+    (the paper chains rigidly, keeping each window's scale);
   * the difference step is one frame (a stride s >= 1 is an option); frames before
     the first full difference (0 and 1 at stride 1) carry no focus; the first
     difference of Eq. 2 alone gives the velocity-based projection the paper
@@ -30,8 +33,9 @@ import math
 
 import numpy as np
 
-ANCHOR_YAW = 0   # lock pitch and roll, propagate yaw and translation (the paper's anchoring)
-ANCHOR_SE3 = 1   # full rigid alignment (no lock), used to pin the chaining algebra
+ANCHOR_YAW = 0        # lock pitch and roll, propagate yaw and translation (the paper's anchoring)
+ANCHOR_SE3 = 1        # full rigid alignment (no lock), used to pin the chaining algebra
+ANCHOR_YAW_SCALE = 2  # the paper's anchoring after rescaling the window's translations (see below)
 
 
 # ----------------------------------------------------------------------------- schedule
@@ -101,11 +105,34 @@ def alignment(T_loc_anchor: np.ndarray, T_w_anchor: np.ndarray, mode: int = ANCH
     return A
 
 
+def window_scale(win, Tl: np.ndarray, T_w: np.ndarray) -> float:
+    """Scale of window `win`'s local frame relative to the world chain, from the frames it shares
+    with the windows before it (start .. emit_begin - 1, already in T_w): the summed distances of
+    their camera centres to the anchor's (the last shared frame) in the world, over the same sum
+    in the window's frame.  1 when the shared centres do not move (nothing to measure)."""
+    a = win["emit_begin"] - 1
+    shared = range(win["start"], win["emit_begin"])
+    cw_a, cl_a = camera_centre(T_w[a]), camera_centre(Tl[a - win["start"]])
+    num = sum(np.linalg.norm(camera_centre(T_w[i]) - cw_a) for i in shared)
+    den = sum(np.linalg.norm(camera_centre(Tl[i - win["start"]]) - cl_a) for i in shared)
+    return num / den if den > 1e-12 else 1.0
+
+
+def scale_translation(Tl: np.ndarray, rho: float) -> np.ndarray:
+    """[R | rho t]: every camera centre of the frame scaled by rho about its origin."""
+    out = np.array(Tl, dtype=np.float64, copy=True)
+    out[..., :3, 3] *= rho
+    return out
+
+
 def chain_windows(schedule, local_poses, mode: int = ANCHOR_YAW) -> np.ndarray:
     """Stitch per-window local poses into world poses of every emitted frame.
 
     schedule: output of window_schedule; local_poses[k]: [size_k, 4, 4] world(window-local)
     -> camera poses of window k.  Window 0 defines the world frame.  Returns [N, 4, 4].
+    ANCHOR_YAW_SCALE first rescales window k's translations by window_scale (monocular windows
+    carry independent scale; the paper's rigid chaining keeps each window's), then anchors as
+    ANCHOR_YAW.
     """
     n = schedule[-1]["emit_end"] if schedule else 0
     T_w = np.zeros((n, 4, 4))
@@ -117,7 +144,9 @@ def chain_windows(schedule, local_poses, mode: int = ANCHOR_YAW) -> np.ndarray:
             a = win["emit_begin"] - 1
             if a < win["start"]:
                 raise ValueError("consecutive windows share no frame (overlap 0)")
-            A = alignment(Tl[a - win["start"]], T_w[a], mode)
+            if mode == ANCHOR_YAW_SCALE:
+                Tl = scale_translation(Tl, window_scale(win, Tl, T_w))
+            A = alignment(Tl[a - win["start"]], T_w[a], ANCHOR_YAW if mode == ANCHOR_YAW_SCALE else mode)
         for t in range(win["emit_begin"], win["emit_end"]):
             T_w[t] = Tl[t - win["start"]] @ A
     return T_w

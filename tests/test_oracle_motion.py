@@ -89,6 +89,44 @@ def test_yaw_lock_exact_for_yaw_only_frames():
     np.testing.assert_allclose(got, T_w, atol=1e-11)
 
 
+def test_scale_aware_chaining_undoes_per_window_scale():
+    """Windows whose frames are a yaw plus shift of the world with their own scale (translations,
+    hence centres, times lambda_k; window 0 at the world's): the scale-aware chaining recovers the
+    trajectory exactly; the rigid one does not; with all lambda = 1 both agree."""
+    rng = np.random.default_rng(9)
+    N, L, O = 64, 16, 8
+    T_w = _trajectory(N, rng)
+    sched = motion.window_schedule(N, L, O)
+
+    def locals_(lams):
+        out = []
+        for k, w in enumerate(sched):
+            g = np.eye(4)
+            if k:
+                g[:3, :3] = mf_synth.rot_y(rng.uniform(-3, 3))
+                g[:3, 3] = rng.uniform(-5, 5, size=3)
+            Tl = np.stack([T_w[t] @ np.linalg.inv(g) for t in range(w["start"], w["start"] + w["size"])])
+            Tl[:, :3, 3] *= lams[k]
+            out.append(Tl)
+        return out
+
+    lams = [1.0] + list(rng.uniform(0.5, 2.0, len(sched) - 1))
+    loc = locals_(lams)
+    got = motion.chain_windows(sched, loc, motion.ANCHOR_YAW_SCALE)
+    np.testing.assert_allclose(got, T_w, atol=1e-10)
+    rigid = motion.chain_windows(sched, loc, motion.ANCHOR_YAW)
+    assert np.abs(rigid - T_w).max() > 1e-2
+    loc1 = locals_([1.0] * len(sched))
+    np.testing.assert_allclose(motion.chain_windows(sched, loc1, motion.ANCHOR_YAW_SCALE),
+                               motion.chain_windows(sched, loc1, motion.ANCHOR_YAW), atol=1e-11)
+
+
+def test_window_scale_is_one_without_motion():
+    T = np.tile(np.eye(4), (6, 1, 1))
+    win = dict(start=0, size=6, emit_begin=3, emit_end=6)
+    assert motion.window_scale(win, T, T) == 1.0
+
+
 def test_yaw_lock_drops_pitch_and_keeps_anchor_centre():
     """A local frame with yaw psi then pitch theta (Y-X order): the alignment keeps exactly R_y(psi),
     and the anchor camera's centre is continuous across the boundary."""
