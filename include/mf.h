@@ -47,6 +47,10 @@ typedef int32_t mf_status;
 /* anchoring modes */
 #define MF_ANCHOR_YAW 0 /* lock pitch and roll, propagate yaw and translation (the paper) */
 #define MF_ANCHOR_SE3 1 /* full rigid alignment (no lock) */
+#define MF_ANCHOR_YAW_SCALE 2 /* MF_ANCHOR_YAW after rescaling the window's translations by the ratio
+                                 of its shared frames' camera-centre distances to the anchor in the
+                                 world chain and in the window (monocular windows carry their own
+                                 scale; the paper's rigid chaining keeps it) */
 
 /* Motion vector of the focus (Sec. 2.3), differences over s = diff_stride frames: */
 #define MF_FOCUS_ACCEL 0    /* a_w = p_t - 2 p_{t-s} + p_{t-2s} (Eq. 3 at s = 1; the paper's focus) */
@@ -93,7 +97,7 @@ typedef struct mf_stream_cfg {
   int32_t window, overlap;      /* L and O, 1 <= O < L: consecutive windows share O frames */
   double fx, fy, cx, cy;        /* pinhole intrinsics (Eq. 5) */
   int32_t n_points;             /* N of Eq. 7, 1..32 */
-  int32_t anchor_mode;          /* MF_ANCHOR_YAW or MF_ANCHOR_SE3 */
+  int32_t anchor_mode;          /* MF_ANCHOR_YAW, MF_ANCHOR_SE3 or MF_ANCHOR_YAW_SCALE */
   double sigma;                 /* Eq. 7 scale: spread = clip(sigma * |a_w,i|, sigma_min, sigma_max) px */
   double sigma_min, sigma_max;  /* 0 => 0.5 and 4 * max(H, W) */
   int32_t emit_maps;            /* 1: render the focus map of every emitted frame */

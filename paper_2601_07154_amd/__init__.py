@@ -11,7 +11,8 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (FOCUS_DTYPE, MF_ANCHOR_SE3, MF_ANCHOR_YAW, MF_BF16, MF_DEVICE_PTR, MF_EAGAIN, MF_ECLOSED,
+from ._lib import (FOCUS_DTYPE, MF_ANCHOR_SE3, MF_ANCHOR_YAW, MF_ANCHOR_YAW_SCALE, MF_FOCUS_ACCEL,
+                   MF_FOCUS_VELOCITY, MF_BF16, MF_DEVICE_PTR, MF_EAGAIN, MF_ECLOSED,
                    MF_EOS, MF_FP32, MF_OK, MF_POSES_LOCAL)
 
 PRECISIONS = {"fp32": MF_FP32, "bf16": MF_BF16, "fp8": _lib.MF_FP8}

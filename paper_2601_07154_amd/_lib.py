@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libmfocus.so")
 
 MF_OK, MF_EINVAL, MF_ENOMEM, MF_EAGAIN, MF_ECLOSED, MF_EDEVICE, MF_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 MF_FP32, MF_BF16, MF_FP8 = 0, 1, 2
-MF_ANCHOR_YAW, MF_ANCHOR_SE3 = 0, 1
+MF_ANCHOR_YAW, MF_ANCHOR_SE3, MF_ANCHOR_YAW_SCALE = 0, 1, 2
+MF_FOCUS_ACCEL, MF_FOCUS_VELOCITY = 0, 1
 MF_EOS, MF_DEVICE_PTR, MF_POSES_LOCAL = 1, 2, 4
 
 

@@ -413,7 +413,7 @@ mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream
     set_err("n_points must be in 1..32");
     return MF_EINVAL;
   }
-  if (c.anchor_mode != MF_ANCHOR_YAW && c.anchor_mode != MF_ANCHOR_SE3) {
+  if (c.anchor_mode != MF_ANCHOR_YAW && c.anchor_mode != MF_ANCHOR_SE3 && c.anchor_mode != MF_ANCHOR_YAW_SCALE) {
     set_err("unknown anchor mode %d", c.anchor_mode);
     return MF_EINVAL;
   }

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
                                                          const float* __restrict__ pose9,
                                                          mf_focus* __restrict__ out) {
   __shared__ double A[16];
+  __shared__ double rho;   // scale of the window's translations (MF_ANCHOR_YAW_SCALE), else 1
   const ChainGroup gr = groups[blockIdx.x];
   for (int wi = gr.first_win; wi < gr.first_win + gr.n_win; ++wi) {
     const ChainWin w = wins[wi];
@@ -73,9 +74,34 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
     FrameHist* hist = sd.hist;
     const int mask = sd.hist_mask;
     if (threadIdx.x == 0) {
+      rho = 1.0;
       if (w.mode == CHAIN_ANCHOR) {
         const int64_t a = w.emit_begin - 1;
-        alignment(T_loc + (int64_t)(w.loc_off + (a - w.start)) * 16, hist[a & mask].T, sd.anchor_mode, A);
+        const double* Tla = T_loc + (int64_t)(w.loc_off + (a - w.start)) * 16;
+        if (sd.anchor_mode == MF_ANCHOR_YAW_SCALE) {
+          // summed centre distances to the anchor over the shared frames, world over window
+          double cwa[3], cla[3], num = 0.0, den = 0.0;
+          centre(hist[a & mask].T, cwa);
+          centre(Tla, cla);
+          for (int64_t i = w.start; i < w.emit_begin; ++i) {
+            double cw[3], cl[3];
+            centre(hist[i & mask].T, cw);
+            centre(T_loc + (int64_t)(w.loc_off + (i - w.start)) * 16, cl);
+            num += sqrt((cw[0] - cwa[0]) * (cw[0] - cwa[0]) + (cw[1] - cwa[1]) * (cw[1] - cwa[1]) +
+                        (cw[2] - cwa[2]) * (cw[2] - cwa[2]));
+            den += sqrt((cl[0] - cla[0]) * (cl[0] - cla[0]) + (cl[1] - cla[1]) * (cl[1] - cla[1]) +
+                        (cl[2] - cla[2]) * (cl[2] - cla[2]));
+          }
+          if (den > 1e-12) rho = num / den;
+          double Ts[16];
+          for (int i = 0; i < 16; ++i) Ts[i] = Tla[i];
+          Ts[3] *= rho;
+          Ts[7] *= rho;
+          Ts[11] *= rho;
+          alignment(Ts, hist[a & mask].T, MF_ANCHOR_YAW, A);
+        } else {
+          alignment(Tla, hist[a & mask].T, sd.anchor_mode, A);
+        }
       } else {
         for (int i = 0; i < 16; ++i) A[i] = (i % 5 == 0) ? 1.0 : 0.0;
       }
@@ -89,8 +115,12 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
       if (w.mode == CHAIN_WORLD) {
         for (int i = 0; i < 16; ++i) h.T[i] = Tl[i];
       } else {
-        double Tw[16];
-        mat4_mul(Tl, A, Tw);
+        double Ts[16], Tw[16];
+        for (int i = 0; i < 16; ++i) Ts[i] = Tl[i];
+        Ts[3] *= rho;
+        Ts[7] *= rho;
+        Ts[11] *= rho;
+        mat4_mul(Ts, A, Tw);
         for (int i = 0; i < 16; ++i) h.T[i] = Tw[i];
       }
     }

@@ -25,12 +25,13 @@ def _drain(eng, sid, H, W, cap=4096):
     return np.concatenate(recs), np.concatenate(maps)
 
 
-def _run_poses_engine(m, T, K, H, W, sigma, n_points=15, local_windows=None, focus_mode=0, diff_stride=1):
+def _run_poses_engine(m, T, K, H, W, sigma, n_points=15, local_windows=None, focus_mode=0, diff_stride=1,
+                      anchor_mode=0):
     eng = m.Engine(1, 128, 4, 128, np.zeros(mf_synth.weight_count(mf_synth.ModelConfig(1, 128, 4, 128)),
                                             np.float32), precision="fp32", max_tokens=16384)
     n = len(T) if T is not None else sum(len(t) for _, t in local_windows)
     sid = eng.open_stream(H, W, 16, 8, K, n_points=n_points, sigma=sigma, result_frames=max(64, n),
-                          focus_mode=focus_mode, diff_stride=diff_stride)
+                          focus_mode=focus_mode, diff_stride=diff_stride, anchor_mode=anchor_mode)
     if local_windows is None:
         eng.push_poses(sid, T, 0, eos=True)
     else:
@@ -108,6 +109,36 @@ def test_focus_modes_and_strides_match_oracle(focus_mode, stride):
     np.testing.assert_allclose(recs["u"][v], tr["uv"][v, 0], rtol=1e-9)
     np.testing.assert_allclose(recs["v"][v], tr["uv"][v, 1], rtol=1e-9)
     np.testing.assert_allclose(maps, ref["maps"], atol=1e-5)
+
+
+def test_scale_aware_anchoring_matches_oracle():
+    """Window-local poses with a per-window scale (translations times lambda_k) chained with
+    MF_ANCHOR_YAW_SCALE: equal to the oracle's scale-aware chaining and to the true trajectory."""
+    torch_cuda()
+    m = mf()
+    rng = np.random.default_rng(12)
+    N, L, O = 56, 16, 8
+    path = mf_synth.CameraPath(velocity=(0.1, 0, 1.2), accel=(0, 0.05, 0.4), sway_deg=4.0)
+    T_w = path.poses(N)
+    sched = motion.window_schedule(N, L, O)
+    wins, locs = [], []
+    for k, w in enumerate(sched):
+        G = np.eye(4)
+        lam = 1.0
+        if k:
+            G[:3, :3] = mf_synth.rot_y(rng.uniform(-2, 2))
+            G[:3, 3] = rng.uniform(-3, 3, 3)
+            lam = rng.uniform(0.5, 2.0)
+        Tl = np.stack([T_w[t] @ np.linalg.inv(G) for t in range(w["start"], w["start"] + w["size"])])
+        Tl[:, :3, 3] *= lam
+        wins.append((w["start"], Tl))
+        locs.append(Tl)
+    K = (400.0, 400.0, 126.0, 70.0)
+    recs, _ = _run_poses_engine(m, None, K, 140, 252, 1e4, local_windows=wins, anchor_mode=m.MF_ANCHOR_YAW_SCALE)
+    chained = motion.chain_windows(sched, locs, motion.ANCHOR_YAW_SCALE)
+    got = recs["T_w2c"].reshape(-1, 4, 4)
+    np.testing.assert_allclose(got, chained, atol=1e-12)
+    np.testing.assert_allclose(got, T_w, atol=1e-9)
 
 
 def test_local_poses_anchoring_matches_oracle():
