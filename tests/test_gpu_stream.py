@@ -194,9 +194,11 @@ def test_tiny_stream_end_to_end(prec):
         assert err_T < 0.05
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_graph_replays_match_eager(precision):
     """A batch shape is captured once as a hipGraph and replayed: every replay (with unrelated eager
-    work and synchronisation in between) equals the eager launch sequence bit for bit."""
+    work and synchronisation in between) equals the eager launch sequence bit for bit (fp8: the
+    per-window amax buffers are cleared by a kernel inside the graph on every replay)."""
     torch = torch_cuda()
     m = mf()
     model = mf_synth.ModelConfig(4, 384, 6, 1536)
@@ -214,10 +216,10 @@ def test_graph_replays_match_eager():
         eng.poll(sid, 1)
         return r, mp
 
-    eager = m.Engine.from_model(model, blob, precision="bf16", max_tokens=8192, graphs=False)
+    eager = m.Engine.from_model(model, blob, precision=precision, max_tokens=8192, graphs=False)
     ref, ref_maps = run(eager)
     eager.close()
-    eng = m.Engine.from_model(model, blob, precision="bf16", max_tokens=8192, graphs=True)
+    eng = m.Engine.from_model(model, blob, precision=precision, max_tokens=8192, graphs=True)
     x = torch.randn(64, 384, device="cuda")
     for rep in range(4):
         got, maps = run(eng)
