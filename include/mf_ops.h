@@ -33,7 +33,8 @@ mf_status mf_forward_window(mf_engine* e, const float* frames_dev, int32_t S, in
 
 /* Diagnostics: copy the first `bytes` of an internal buffer, as left by the last batch or
  * mf_forward_window, to host memory.  which: 0 residual X (fp32 [rows][dim]), 1 LayerNorm output
- * ([rows][dim]), 2 Q, 3 K, 4 Vt (layouts above; mpad is max_tokens_per_batch rounded up to 8,
+ * ([rows][dim]), 2 Q (stored multiplied by log2(e)/sqrt(head_dim), the form the attention kernels
+ * take), 3 K, 4 Vt (layouts above; mpad is max_tokens_per_batch rounded up to 8,
  * plus 256), 5 attention output O
  * ([rows][dim]), 6 MLP hidden / patch matrix ([rows][max(mlp, 640)]); element type T of the
  * engine's precision except X.  MF_EINVAL beyond the buffer. */

@@ -4,7 +4,9 @@
 // so every frame starts 16-byte aligned in the transposed V layout).  Frame-wise layers use
 // one segment per frame, global layers one segment per window; keys in the padding rows
 // between frames are masked.  softmax(Q K^T / sqrt(hd)) V is computed per head with the
-// running-max rescaling of flash attention: scores never leave registers.
+// running-max rescaling of flash attention: scores never leave registers.  The queries arrive
+// multiplied by log2(e)/sqrt(hd) (the QKV projection applies the factor before rounding), so a
+// score is directly the base-2 exponent of its unnormalised probability.
 //
 // attn_kernel (fp32, and bf16 with hd 32): each workgroup (4 waves) takes 128 queries of one
 // segment and one head; each wave owns 32 queries.  attn_kernel_v3 (bf16, hd 64) doubles the
@@ -112,8 +114,7 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
                                                    const T* __restrict__ Vt, T* __restrict__ O,
                                                    int64_t mpad, int heads, int dim,
                                                    const AttnSeg* __restrict__ segs,
-                                                   const AttnWork* __restrict__ work, int nwork,
-                                                   float scale_log2) {
+                                                   const AttnWork* __restrict__ work, int nwork) {
   using C = AttnCfg<T, HD>;
   constexpr int BK = C::BK;
   __shared__ u32x4 sK[2][C::KCH];
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
 #pragma unroll
       for (int r = 0; r < 16; ++r) mx = fmaxf(mx, s[kb][r]);
     mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-    const float m_new = fmaxf(m_run, mx * scale_log2);
+    const float m_new = fmaxf(m_run, mx);
     const float alpha = exp2f(m_run - m_new);
     m_run = m_new;
     float ls = 0.0f;
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
     for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float p = exp2f(fmaf(s[kb][r], scale_log2, -m_new));
+        const float p = exp2f(s[kb][r] - m_new);
         s[kb][r] = p;
         ls += p;
       }
@@ -273,8 +274,9 @@ __global__ __launch_bounds__(256) void attn_kernel(const T* __restrict__ Q, cons
 // staged in LDS tiles of 128 (double-buffered, one barrier per tile; the next tile passes
 // through 16 registers per thread, K during the first steps, V after) and consumed in 32-key
 // steps, unrolled four to a tile so every LDS offset is a constant.  Per step:
-//  - S^T = K Q^T; the exp2 argument s c - m (c = log2(e)/sqrt(hd), m the query's reference in
-//    log2 units) is one fma per score;
+//  - S^T = K Q^T is accumulated onto -m (m the query's reference), so the MFMA result is the
+//    exp2 argument itself: no VALU work per score before the exp (the -m block is rewritten
+//    only when m changes);
 //  - m is set from the query's first-step maximum and raised only when a step's probabilities
 //    grow large (a lane's partial row sum above 2^12, which also catches an overflow to inf);
 //    no per-step maximum is computed otherwise, and the O rescale is rare;
@@ -304,16 +306,19 @@ MF_DEV float pair_sum(float v) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// p = exp2(s c - m) as bf16 pairs (the B operand of PV, keys 4g.., 8+4g.. per 16-key half) and the
-// lane's partial row sum over those probabilities
-MF_DEV void probs(const f32x16& s, float c, float m, u32x4 (&pf)[2], float& ls) {
+// p = exp2(s - d) as bf16 pairs (the B operand of PV, keys 4g.., 8+4g.. per 16-key half) and the
+// lane's partial row sum over those probabilities; s already holds the exponent relative to the
+// reference, d is a further shift (a raised reference), used only when `shift` is set
+MF_DEV void probs(const f32x16& s, float d, u32x4 (&pf)[2], float& ls, bool shift) {
   const bf16x2_t ones = {(bf16)1.0f, (bf16)1.0f};
   float acc = 0.0f;
 #pragma unroll
   for (int j2 = 0; j2 < 2; ++j2)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const f32x2 e = {fast_exp2(fmaf(s[8 * j2 + 2 * q], c, -m)), fast_exp2(fmaf(s[8 * j2 + 2 * q + 1], c, -m))};
+      const float a0 = shift ? s[8 * j2 + 2 * q] - d : s[8 * j2 + 2 * q];
+      const float a1 = shift ? s[8 * j2 + 2 * q + 1] - d : s[8 * j2 + 2 * q + 1];
+      const f32x2 e = {fast_exp2(a0), fast_exp2(a1)};
       const bf16x2_t pr = __builtin_convertvector(e, bf16x2_t);
       acc = __builtin_amdgcn_fdot2_f32_bf16(pr, ones, acc, false);
       pf[j2][q] = __builtin_bit_cast(unsigned, pr);
@@ -325,8 +330,7 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
                                                          const bf16* __restrict__ Vt, bf16* __restrict__ O,
                                                          int64_t mpad, int heads, int dim,
                                                          const AttnSeg* __restrict__ segs,
-                                                         const AttnWork* __restrict__ work, int nwork,
-                                                         float c) {
+                                                         const AttnWork* __restrict__ work, int nwork) {
   __shared__ u32x4 sK[2][KT * KCPR];
   __shared__ u32x4 sV[2][HD * VCPR];
   const int nb = nwork * heads;
@@ -396,6 +400,11 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
       for (int r = 0; r < 16; ++r) o[hb][t][r] = 0.0f;
   float l_run[2] = {0.0f, 0.0f};
   float m_cur[2] = {0.0f, 0.0f};   // reference per query (log2 units), set on the first step
+  f32x16 mneg[2];                  // -m_cur in all 16 registers: the accumulator S^T starts from
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) mneg[hb][r] = 0.0f;
 
   const int key_end = sg.nf == 1 ? sg.n : seg_len;
   const int nsteps = (key_end + KS - 1) / KS;
@@ -415,10 +424,10 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
     f32x16 s[2];
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
+      s[hb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf[0], *(const bf16x8*)&qf[hb][0], mneg[hb],
+                                                      0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) s[hb][r] = 0.0f;
-#pragma unroll
-      for (int f = 0; f < 4; ++f)
+      for (int f = 1; f < 4; ++f)
         s[hb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&kf[f], *(const bf16x8*)&qf[hb][f], s[hb],
                                                         0, 0, 0);
     }
@@ -446,24 +455,26 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
     for (int hb = 0; hb < 2; ++hb) {
       u32x4 pf[2];
       float ls;
-      probs(s[hb], c, m_cur[hb], pf, ls);
+      probs(s[hb], 0.0f, pf, ls, false);
       // (re)establish the reference on the first step, or when the probabilities grew large
       if (__any(st == 0 || !(ls <= GROW))) {
         float mx = s[hb][0];
 #pragma unroll
         for (int r = 1; r < 16; ++r) mx = fmaxf(mx, s[hb][r]);
-        mx = pair_max(mx) * c;
         const float m_old = m_cur[hb];
+        mx = pair_max(mx) + m_old;
         float m_new = st == 0 ? mx : fmaxf(m_old, mx);
         m_new = m_new > -INFINITY ? m_new : 0.0f;   // a step with every key masked keeps a finite m
         const float alpha = st == 0 ? 1.0f : fast_exp2(m_old - m_new);
         m_cur[hb] = m_new;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mneg[hb][r] = -m_new;
         l_run[hb] *= alpha;
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
           for (int r = 0; r < 16; ++r) o[hb][t][r] *= alpha;
-        probs(s[hb], c, m_new, pf, ls);
+        probs(s[hb], m_new - m_old, pf, ls, true);
       }
       l_run[hb] += ls;
       // O^T += V^T P^T for this block
@@ -532,14 +543,14 @@ static hipError_t launch(const void* q, const void* k, const void* vt, void* o, 
                          int heads, int dim, const AttnSeg* segs, const AttnWork* work, int nwork,
                          hipStream_t s) {
   if (nwork <= 0) return hipSuccess;
-  const float scale_log2 = (float)(1.4426950408889634 / sqrt((double)HD));
   hipLaunchKernelGGL((attn_kernel<T, HD>), dim3(nwork * heads), dim3(256), 0, s, (const T*)q,
-                     (const T*)k, (const T*)vt, (T*)o, mpad, heads, dim, segs, work, nwork,
-                     scale_log2);
+                     (const T*)k, (const T*)vt, (T*)o, mpad, heads, dim, segs, work, nwork);
   return hipGetLastError();
 }
 
 int attention_q_tile(Dtype dt, int hd) { return (dt == DT_BF16 && hd == 64) ? v3::QT : 128; }
+
+float attention_q_scale(int hd) { return (float)(1.4426950408889634 / sqrt((double)hd)); }
 
 hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void* vt, void* o,
                      int64_t mpad, int heads, int dim, const AttnSeg* segs, const AttnWork* work,
@@ -547,9 +558,8 @@ hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void*
   if (dt == DT_BF16) {
     if (hd == 64) {
       if (nwork <= 0) return hipSuccess;
-      const float c = (float)(1.4426950408889634 / 8.0);
       hipLaunchKernelGGL(v3::attn_kernel_v3, dim3(nwork * heads), dim3(256), 0, s, (const bf16*)q, (const bf16*)k,
-                         (const bf16*)vt, (bf16*)o, mpad, heads, dim, segs, work, nwork, c);
+                         (const bf16*)vt, (bf16*)o, mpad, heads, dim, segs, work, nwork);
       return hipGetLastError();
     }
     if (hd == 32) return launch<bf16, 32>(q, k, vt, o, mpad, heads, dim, segs, work, nwork, s);

@@ -607,6 +607,7 @@ class HipExecutor : public Executor {
       GemmArgs q{};
       q.A = Y_; q.lda = D; q.Bt = L.Wqkv; q.ldb = D; q.M = M; q.N = 3 * D; q.K = D; q.bias = L.b_qkv;
       q.q = Q_; q.k = K_; q.vt = Vt_; q.heads = H_; q.hd = hd_; q.mpad = mpad_;
+      q.qscale = attention_q_scale(hd_);
       if (fp8_) {
         HIPCHECK(quant(Y_, D, Y8_, srow_));
         q.A = Y8_;

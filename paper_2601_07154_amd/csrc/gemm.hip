@@ -68,11 +68,13 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
   const float bs = a.ascale ? a.bscale[0] : 1.0f;
   int which = 0, nbase = 0;
   To* dst = nullptr;
+  float qs = 1.0f;   // QKV: the q block's factor (the attention kernels take scaled queries)
   if constexpr (EPI == EPI_QKV) {
     const int D = a.heads * a.hd;
     which = a.qkv_which0 + n0 / D;
     nbase = (n0 / D) * D;
     dst = (To*)(which == 0 ? a.q : (which == 1 ? a.k : a.vt));
+    if (which == 0 && a.qscale != 0.0f) qs = a.qscale;
   }
   static_assert(WN % 2 == 0, "the staged epilogue takes a wave's columns 64 at a time");
   if constexpr (EPI == EPI_PATCH) {
@@ -136,6 +138,7 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
           f32x4 v = *(const f32x4*)(stage + r * SR + c4);
           const float sc = a.ascale ? a.ascale[m] * bs : 1.0f;
           v = v * sc + bias4;
+          if constexpr (EPI == EPI_QKV) v = v * qs;
           if constexpr (EPI == EPI_RESID) {
             f32x4* c = (f32x4*)((float*)a.C + (int64_t)m * a.ldc + nb);
             *c = *c + v;

@@ -19,6 +19,7 @@ struct GemmArgs {
   // EPI_QKV: Q, K head-major [H][mpad][hd], V transposed [H][hd][mpad]
   void* q; void* k; void* vt; int heads; int hd; int64_t mpad;
   int qkv_which0;                  // block (0 q, 1 k, 2 v) of column 0 of this launch (set internally)
+  float qscale;                    // EPI_QKV: factor on the q block before its rounding (0 reads as 1)
   // fp8 operands: per-row scale of A [M] and the scale of B [1] (device); null otherwise
   const float* ascale; const float* bscale;
   // EPI_PATCH: per-row kind/PE row (rowinfo), PE table [rows][N] fp32, camera tokens
@@ -30,6 +31,12 @@ hipError_t gemm(Dtype dt, Epi epi, const GemmArgs& a, hipStream_t s);
 struct AttnSeg { int32_t base, nf, n, npad; };   // tokens [base, base+nf*npad); frame stride npad, n valid
 struct AttnWork { int32_t seg, q0; };             // a query tile of a segment (attention_q_tile queries)
 int attention_q_tile(Dtype dt, int hd);
+// The kernels take the queries pre-multiplied by attention_q_scale(hd) = log2(e) / sqrt(hd), so
+// that a score is already the exponent of 2 of the softmax (the QKV epilogue applies the factor
+// before rounding to the storage type).
+float attention_q_scale(int hd);
+// y[i] = x[i] * s in fp32, rounded to dt (bf16 or fp32); n elements.
+hipError_t scale_copy(Dtype dt, const void* x, void* y, int64_t n, float s, hipStream_t st);
 hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void* vt, void* o,
                      int64_t mpad, int heads, int dim, const AttnSeg* segs, const AttnWork* work,
                      int nwork, hipStream_t s);

@@ -343,4 +343,22 @@ hipError_t quantize_plain_fp8(const float* x, int64_t n, float scale, fp8* q, hi
   return hipGetLastError();
 }
 
+// Op-level: y[i] = x[i] * s, the product in fp32 rounded to T (the attention op's query scaling).
+template <typename T>
+__global__ void scale_copy_kernel(const T* __restrict__ x, T* __restrict__ y, int64_t n, float s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (T)((float)x[i] * s);
+}
+
+hipError_t scale_copy(Dtype dt, const void* x, void* y, int64_t n, float s, hipStream_t st) {
+  if (n < 0 || (dt != DT_BF16 && dt != DT_F32)) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (dt == DT_BF16)
+    hipLaunchKernelGGL(scale_copy_kernel<bf16>, grid, dim3(256), 0, st, (const bf16*)x, (bf16*)y, n, s);
+  else
+    hipLaunchKernelGGL(scale_copy_kernel<float>, grid, dim3(256), 0, st, (const float*)x, (float*)y, n, s);
+  return hipGetLastError();
+}
+
 }  // namespace mf

@@ -35,13 +35,20 @@ mf_status mf_op_attention(int32_t precision, int32_t head_dim, int32_t heads, in
     for (int q0 = 0; q0 < qend; q0 += qt) wk.push_back({i, q0});
   }
   hipStream_t st = (hipStream_t)stream;
+  const Dtype dt = precision == MF_BF16 ? DT_BF16 : DT_F32;
+  // the kernels take the queries multiplied by log2(e)/sqrt(hd): a scaled copy of q goes first
+  const int64_t nq = (int64_t)heads * mpad * head_dim;
+  const size_t qb = ((size_t)nq * (dt == DT_BF16 ? 2 : 4) + 255) / 256 * 256;
   void* dev = nullptr;
   const size_t sb = sg.size() * sizeof(AttnSeg), wb = wk.size() * sizeof(AttnWork);
-  if (hipMalloc(&dev, sb + wb) != hipSuccess) return MF_EDEVICE;
-  hipMemcpyAsync(dev, sg.data(), sb, hipMemcpyHostToDevice, st);
-  hipMemcpyAsync((char*)dev + sb, wk.data(), wb, hipMemcpyHostToDevice, st);
-  hipError_t r = attention(precision == MF_BF16 ? DT_BF16 : DT_F32, head_dim, q, k, vt, o, mpad, heads, dim,
-                           (const AttnSeg*)dev, (const AttnWork*)((char*)dev + sb), (int)wk.size(), st);
+  if (hipMalloc(&dev, qb + sb + wb) != hipSuccess) return MF_EDEVICE;
+  char* tabs = (char*)dev + qb;
+  hipMemcpyAsync(tabs, sg.data(), sb, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(tabs + sb, wk.data(), wb, hipMemcpyHostToDevice, st);
+  hipError_t r = scale_copy(dt, q, dev, nq, attention_q_scale(head_dim), st);
+  if (r == hipSuccess)
+    r = attention(dt, head_dim, dev, k, vt, o, mpad, heads, dim, (const AttnSeg*)tabs,
+                  (const AttnWork*)(tabs + sb), (int)wk.size(), st);
   hipStreamSynchronize(st);
   hipFree(dev);
   return r == hipSuccess ? MF_OK : MF_EDEVICE;

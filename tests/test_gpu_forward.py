@@ -1,5 +1,7 @@
 """Window forward parity (patch embedding, blocks, pose head) of the HIP path against the FP64
 oracle on the same seeded weights and pixels."""
+import math
+
 import numpy as np
 import pytest
 
@@ -84,7 +86,8 @@ def test_tiny_workload_poses(prec):
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 2e-2)])
 def test_qkv_scatter_layouts(prec, tol):
     """Step-local: the QKV GEMM's epilogue writes Q and K head-major and V transposed exactly
-    as the oracle's q, k, v of the first block (from the same embedded tokens)."""
+    as the oracle's q, k, v of the first block (from the same embedded tokens); Q is stored
+    multiplied by log2(e)/sqrt(hd), the form the attention kernels take."""
     torch = torch_cuda()
     m = mf()
     model = mf_synth.ModelConfig(2, 128, 4, 256)
@@ -100,7 +103,7 @@ def test_qkv_scatter_layouts(prec, tol):
             a = (a.astype(np.uint32) << 16).view(np.float32)
         return a.astype(np.float64)
     hd = model.head_dim
-    Q = fetch(2, (model.heads, mpad, hd))
+    Q = fetch(2, (model.heads, mpad, hd)) * (math.sqrt(hd) / math.log2(math.e))   # stored scaled
     Kb = fetch(3, (model.heads, mpad, hd))
     Vt = fetch(4, (model.heads, hd, mpad))
     n = (H // 14) * (W // 14) + 1

@@ -2,6 +2,8 @@
 24 layers, D=1024): the QKV projection of a window (per-window E4M3 activation scale over all
 110 640 rows, per-tensor E4M3 weights) step-local against the oracle's E4M3 rounding on sampled
 rows, and the window's poses against the BF16 path on the same input."""
+import math
+
 import numpy as np
 import pytest
 
@@ -36,7 +38,8 @@ def _f32(x):
 def test_qkv_projection_full_size(setup):
     """Q, K and V of layer 0 for sampled rows: the oracle takes the device's embedded tokens,
     LayerNorms them in FP64, rounds to bf16, scales by the window's amax/448 and the weights by
-    theirs (both in fp32, as the device does), rounds both to E4M3 and multiplies in FP64."""
+    theirs (both in fp32, as the device does), rounds both to E4M3 and multiplies in FP64.  The
+    device stores Q multiplied by log2(e)/sqrt(hd), which the comparison divides out."""
     s = setup
     m = s["m"]
     D, H = WL.model.dim, WL.model.heads
@@ -64,7 +67,7 @@ def test_qkv_projection_full_size(setup):
     rows = s["valid"][sample_t]
     bf = lambda u: (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
     got = np.concatenate([
-        bf(Q[:, rows, :]).transpose(1, 0, 2).reshape(len(rows), D),
+        bf(Q[:, rows, :]).transpose(1, 0, 2).reshape(len(rows), D) * (math.sqrt(hd) / math.log2(math.e)),
         bf(Kd[:, rows, :]).transpose(1, 0, 2).reshape(len(rows), D),
         bf(Vt[:, :, rows]).transpose(2, 0, 1).reshape(len(rows), D)], axis=1)
     err = np.abs(got - ref)
