@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
       for (int r = 0; r < 16; ++r) o[hb][t][r] = 0.0f;
   float l_run[2] = {0.0f, 0.0f};
   float m_cur[2] = {0.0f, 0.0f};   // reference per query (log2 units), set on the first step
-  f32x16 mneg[2];                  // -m_cur in all 16 registers: the accumulator S^T starts from
+  f32x16 mneg[2];                  // -m_cur in all 16 registers, the value S^T accumulates onto
 #pragma unroll
   for (int hb = 0; hb < 2; ++hb)
 #pragma unroll
