@@ -452,8 +452,12 @@ static hipError_t launch_tile(const GemmArgs& a, hipStream_t s) {
 
 template <typename T, int EPI, int TC>
 static hipError_t launch_shape(const GemmArgs& a, hipStream_t s) {
-  // 256 x 128 tiles (waves of 128 x 64: fewer LDS bytes per MFMA) once there are enough of them
-  if (sizeof(T) <= 2 && (int64_t)((a.M + 255) / 256) * (a.N / 128) >= 512) return launch_tile<T, EPI, 4, 2, TC>(a, s);
+  // 256 x 128 tiles (waves of 128 x 64: fewer LDS bytes per MFMA) once there are enough of them;
+  // E4M3 products narrower than 768 columns run faster on 128 x 128 tiles (measured: 12% on
+  // N = 384, K = 1536)
+  const bool wide = sizeof(T) == 2 || a.N >= 768;
+  if (sizeof(T) <= 2 && wide && (int64_t)((a.M + 255) / 256) * (a.N / 128) >= 512)
+    return launch_tile<T, EPI, 4, 2, TC>(a, s);
   return launch_tile<T, EPI, 2, 2, TC>(a, s);
 }
 
