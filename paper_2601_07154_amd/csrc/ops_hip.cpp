@@ -43,13 +43,14 @@ mf_status mf_op_attention(int32_t precision, int32_t head_dim, int32_t heads, in
   const size_t sb = sg.size() * sizeof(AttnSeg), wb = wk.size() * sizeof(AttnWork);
   if (hipMalloc(&dev, qb + sb + wb) != hipSuccess) return MF_EDEVICE;
   char* tabs = (char*)dev + qb;
-  hipMemcpyAsync(tabs, sg.data(), sb, hipMemcpyHostToDevice, st);
-  hipMemcpyAsync(tabs + sb, wk.data(), wb, hipMemcpyHostToDevice, st);
-  hipError_t r = scale_copy(dt, q, dev, nq, attention_q_scale(head_dim), st);
+  hipError_t r = hipMemcpyAsync(tabs, sg.data(), sb, hipMemcpyHostToDevice, st);
+  if (r == hipSuccess) r = hipMemcpyAsync(tabs + sb, wk.data(), wb, hipMemcpyHostToDevice, st);
+  if (r == hipSuccess) r = scale_copy(dt, q, dev, nq, attention_q_scale(head_dim), st);
   if (r == hipSuccess)
     r = attention(dt, head_dim, dev, k, vt, o, mpad, heads, dim, (const AttnSeg*)tabs,
                   (const AttnWork*)(tabs + sb), (int)wk.size(), st);
-  hipStreamSynchronize(st);
+  const hipError_t rs = hipStreamSynchronize(st);   // the host tables and the copy must outlive the launches
+  if (r == hipSuccess) r = rs;
   hipFree(dev);
   return r == hipSuccess ? MF_OK : MF_EDEVICE;
 }
