@@ -35,9 +35,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
     """HBM bytes per global-attention launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary, if it was taken on the current kernel source (else None)."""
+    summary, if it was taken on this workload and the current kernel source (else None)."""
     import re
     try:
         text = open(TRAFFIC_FILE).read()
@@ -45,7 +45,8 @@ def measured_traffic():
         return None
     src = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not src or not val or src.group(1) != kernel_source_hash():
+    wl = re.search(r"workload:\s*(\S+)", text)
+    if not src or not val or not wl or src.group(1) != kernel_source_hash() or wl.group(1) != workload:
         return None
     return float(val.group(1))
 
@@ -276,7 +277,7 @@ def main():
     res["roofline"] = {"kernel": "global flash attention (attn_kernel_v3, bf16, hd 64)", "bound": "mfma",
                        "achieved": ach, "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
                        "frac": ach / PEAK_TFLOPS[args.precision],
-                       "traffic": measured_traffic() if args.precision == "bf16" else None,
+                       "traffic": measured_traffic(wl.name) if args.precision == "bf16" else None,
                        "avg_launch_ms": avg_ms, "launches": prof["attn_global_calls"],
                        "flops_per_launch": flops}
     res["stage_ms_per_step"] = {"attn_global": prof["attn_global_ms"] / args.steps,

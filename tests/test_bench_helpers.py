@@ -30,3 +30,18 @@ def test_flop_counts_small_workload():
     T = wl.window * wl.tokens_per_frame
     assert b.global_attention_flops(wl) == 7 * 4.0 * T * T * wl.model.dim
     assert abs(b.global_attention_flops(wl) - 1.4309e12) / 1.4309e12 < 1e-4
+
+
+def test_traffic_figure_only_for_its_workload_and_source(tmp_path, monkeypatch):
+    """roofline.traffic comes from the committed counter summary only for the workload and the
+    attention source it was measured on."""
+    b = _bench()
+    text = (f"source_sha256: {b.kernel_source_hash()}\ntraffic_bytes_per_launch: 123456\n"
+            f"workload: {mf_synth.SMALL.name}\n")
+    f = tmp_path / "traffic.md"
+    f.write_text(text)
+    monkeypatch.setattr(b, "TRAFFIC_FILE", str(f))
+    assert b.measured_traffic(mf_synth.SMALL.name) == 123456.0
+    assert b.measured_traffic(mf_synth.LARGE.name) is None
+    f.write_text(text.replace(b.kernel_source_hash(), "0" * 64))
+    assert b.measured_traffic(mf_synth.SMALL.name) is None
