@@ -25,7 +25,8 @@ Readings of points the paper leaves open (each is a project decision):
   * a focus is valid iff |a_w| > 1e-12 max(1, |p_t|) and |a_c,z| > 1e-6 |a_c|;
   * map points are the last N valid accelerations rotated by the current
     camera's rotation; spread clip(sigma*s_i, sigma_min, sigma_max) pixels with
-    s_i = |a_w,i|; Z = max of the unnormalised map (0 map if Z < 1e-30).
+    s_i = |a_w,i|; Z = max of the unnormalised map (peak 1), or as an option Z = its sum
+    over the pixel grid (a probability map); 0 map if Z < 1e-30 in either mode.
 """
 from __future__ import annotations
 
@@ -216,20 +217,34 @@ def map_points(t: int, T_w: np.ndarray, track: dict, n_points: int, fx, fy, cx, 
         if not abs(a[2]) > 1e-6 * np.linalg.norm(a):
             continue
         u, v = project(a, fx, fy, cx, cy)
-        sig = min(max(sigma * track["s"][i], sigma_min), sigma_max)
-        pts.append((u, v, sig))
+        pts.append((u, v, spread(track["s"][i], sigma, sigma_min, sigma_max)))
     return pts
 
 
-def focus_map(points, height: int, width: int):
+MAP_MAX = 0   # Z = the largest value of the unnormalised map: the peak of M is 1
+MAP_SUM = 1   # Z = the sum of the unnormalised map over the pixel grid: M sums to 1
+
+
+def spread(s: float, sigma: float, sigma_min: float, sigma_max: float) -> float:
+    """Eq. 7's spread of a motion point in pixels: sigma times its magnitude s, clipped."""
+    return min(max(sigma * s, sigma_min), sigma_max)
+
+
+def focus_map(points, height: int, width: int, z_mode: int = MAP_MAX):
     """Eq. 7: M(x, y) = (1/Z) sum_i exp(-((x-u_i)^2 + (y-v_i)^2) / (2 sigma_i^2)) on the
-    integer pixel grid, Z = max over the grid.  Returns (M [H,W], Z, argmax index)."""
+    integer pixel grid; Z = the map's maximum (MAP_MAX) or its sum over the grid (MAP_SUM).
+    Returns (M [H,W], Z, argmax index); the argmax does not depend on the mode."""
+    if z_mode not in (MAP_MAX, MAP_SUM):
+        raise ValueError("z_mode must be MAP_MAX or MAP_SUM")
     ys = np.arange(height, dtype=np.float64)[:, None]
     xs = np.arange(width, dtype=np.float64)[None, :]
     G = np.zeros((height, width))
     for (u, v, sig) in points:
         G += np.exp(-((xs - u) ** 2 + (ys - v) ** 2) / (2.0 * sig * sig))
-    Z = float(G.max()) if G.size else 0.0
+    if not G.size:
+        Z = 0.0
+    else:
+        Z = float(G.max()) if z_mode == MAP_MAX else float(G.sum())
     if Z < 1e-30:
         return np.zeros_like(G), Z, 0
     M = G / Z

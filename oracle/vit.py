@@ -26,6 +26,7 @@ Options
 from __future__ import annotations
 
 import math
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 from scipy.special import erf
@@ -185,27 +186,39 @@ def attention(q: np.ndarray, k: np.ndarray, v: np.ndarray, prec: Prec | None = N
     return out
 
 
-def multihead(xn: np.ndarray, lw: dict, heads: int, groups: list, prec: Prec) -> np.ndarray:
+def multihead(xn: np.ndarray, lw: dict, heads: int, groups: list, prec: Prec,
+              workers: int = 1) -> np.ndarray:
     """Self-attention of the LayerNormed tokens xn [T, D] within each token group.
 
     groups: list of (start, length) token ranges; tokens attend only inside their group.
     Returns the output projection O W_o + b_o [T, D].
+    workers > 1 computes the heads on that many threads (the heads are independent and each
+    writes its own columns of O, so the values are the same as with one worker; NumPy releases
+    the interpreter lock inside its array loops, which is what makes the threads run at once).
     """
     T, D = xn.shape
     hd = D // heads
     qkv = prec.matmul_q(xn, lw["W_qkv"]) + lw["b_qkv"]
     q, k, v = qkv[:, :D], qkv[:, D:2 * D], qkv[:, 2 * D:]
     o = np.empty((T, D), dtype=np.float64)
-    for (s, n) in groups:
-        for h in range(heads):
-            c = slice(h * hd, (h + 1) * hd)
+
+    def one_head(h):
+        c = slice(h * hd, (h + 1) * hd)
+        for (s, n) in groups:
             o[s:s + n, c] = attention(q[s:s + n, c], k[s:s + n, c], v[s:s + n, c], prec)
+
+    if workers > 1:
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(one_head, range(heads)))
+    else:
+        for h in range(heads):
+            one_head(h)
     return prec.matmul(o, lw["W_o"]) + lw["b_o"]
 
 
-def block(x: np.ndarray, lw: dict, heads: int, groups: list, prec: Prec) -> np.ndarray:
+def block(x: np.ndarray, lw: dict, heads: int, groups: list, prec: Prec, workers: int = 1) -> np.ndarray:
     """One pre-LN transformer block: X += Attn(LN1 X); X += W2 GELU(W1 LN2 X)."""
-    x = x + multihead(layer_norm(x, lw["ln1_g"], lw["ln1_b"]), lw, heads, groups, prec)
+    x = x + multihead(layer_norm(x, lw["ln1_g"], lw["ln1_b"]), lw, heads, groups, prec, workers)
     h = gelu(prec.matmul_q(layer_norm(x, lw["ln2_g"], lw["ln2_b"]), lw["W_1"]) + lw["b_1"])
     return x + prec.matmul_q(h, lw["W_2"]) + lw["b_2"]
 
@@ -252,10 +265,11 @@ def pose9_to_T(p9: np.ndarray) -> np.ndarray:
 
 
 def forward_window(frames: np.ndarray, w: dict, heads: int, patch: int = 14,
-                   precision: str = "fp64", return_tokens: bool = False):
+                   precision: str = "fp64", return_tokens: bool = False, workers: int = 1):
     """Pose regression for one window of S frames [S,3,H,W] -> pose9 [S, 9].
 
     Even layers attend within each frame (n = P+1 tokens), odd layers over all S*n tokens.
+    workers: threads over the attention heads (same values for any count).
     """
     prec = Prec(precision)
     S, _, H, W = frames.shape
@@ -264,6 +278,6 @@ def forward_window(frames: np.ndarray, w: dict, heads: int, patch: int = 14,
     frame_groups = [(f * n, n) for f in range(S)]
     window_group = [(0, S * n)]
     for l, lw in enumerate(w["layers"]):
-        x = block(x, lw, heads, frame_groups if l % 2 == 0 else window_group, prec)
+        x = block(x, lw, heads, frame_groups if l % 2 == 0 else window_group, prec, workers)
     p9 = pose_head(x[0::n], w)
     return (p9, x) if return_tokens else p9

@@ -287,6 +287,50 @@ def test_map_is_linear_before_normalisation_and_ties_go_low():
     assert Zf < 1e-30 and not far.any()
 
 
+def test_sum_normalised_map_single_point():
+    """Z = the sum over the grid: a single Gaussian is separable, so the normalised value at (x, y) is
+    the product of the two 1-D normal densities at x - u and y - v, each divided by its own sum over
+    the grid's columns / rows (scipy's density, independent of the oracle's formula); M sums to 1."""
+    H, W, u, v, sig = 36, 50, 21.3, 14.6, 3.5
+    M, Z, am = motion.focus_map([(u, v, sig)], H, W, motion.MAP_SUM)
+    px = norm.pdf(np.arange(W) - u, scale=sig)
+    py = norm.pdf(np.arange(H) - v, scale=sig)
+    ref = np.outer(py / py.sum(), px / px.sum())
+    np.testing.assert_allclose(M, ref, rtol=1e-12, atol=1e-18)
+    assert abs(M.sum() - 1.0) < 1e-12
+    assert am == int(np.argmax(ref))
+
+
+def test_sum_and_max_normalisations_differ_by_one_factor():
+    """The two normalisers of Eq. 7 give the same map up to Z_max / Z_sum, the same argmax, and the
+    same zero map when nothing projects."""
+    H, W = 30, 44
+    pts = [(8.0, 10.0, 3.0), (20.5, 12.25, 5.0), (35.0, 4.0, 1.5)]
+    Mm, Zm, am_m = motion.focus_map(pts, H, W, motion.MAP_MAX)
+    Ms, Zs, am_s = motion.focus_map(pts, H, W, motion.MAP_SUM)
+    np.testing.assert_allclose(Ms * (Zs / Zm), Mm, rtol=1e-13, atol=1e-16)
+    assert am_m == am_s and Ms.max() < 1.0 and abs(Ms.sum() - 1.0) < 1e-12
+    M0, Z0, a0 = motion.focus_map([], H, W, motion.MAP_SUM)
+    assert Z0 == 0 and not M0.any() and a0 == 0
+    with pytest.raises(ValueError):
+        motion.focus_map(pts, H, W, 2)
+
+
+def test_sigma_px_closed_form():
+    """Each frame's own spread (Eq. 7) on a constant-acceleration path: the second difference of the
+    centres is a dt^2 exactly, so sigma_px = clip(sigma |a| dt^2, sigma_min, sigma_max) from frame 2 on
+    and 0 on frames 0 and 1 (no focus point)."""
+    from oracle import pipeline
+    fps, acc = 30.0, (0.3, 0.0, 0.8)
+    T_w = mf_synth.CameraPath(accel=acc, sway_deg=0.0).poses(12)
+    s_ref = np.linalg.norm(acc) / fps ** 2
+    for sigma, lo, hi in ((1e4, 0.5, 2000.0), (1.0, 0.5, 2000.0), (1e9, 0.5, 40.0)):
+        out = pipeline.run_poses(T_w, K, 40, 60, sigma=sigma, sigma_min=lo, sigma_max=hi, maps=False)
+        sp = out["sigma_px"]
+        assert sp[0] == 0.0 and sp[1] == 0.0
+        np.testing.assert_allclose(sp[2:], min(max(sigma * s_ref, lo), hi), rtol=1e-9)
+
+
 def test_map_points_use_current_rotation():
     """Constant world acceleration along z and a camera whose yaw changes per frame: every point of
     frame t projects to cx - fx tan(yaw_t)."""
