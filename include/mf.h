@@ -57,6 +57,10 @@ typedef int32_t mf_status;
 #define MF_FOCUS_VELOCITY 1 /* v = p_t - p_{t-s} (Eq. 2): the velocity-based projection the paper
                                contrasts with (focus of expansion) */
 
+/* Normaliser Z of the focus map (Eq. 7): */
+#define MF_MAP_MAX 0        /* Z = the map's largest value: the peak is 1 (the default) */
+#define MF_MAP_SUM 1        /* Z = the map's sum over the pixel grid: M is a probability map */
+
 /* push flags */
 #define MF_EOS 1          /* these are the stream's last frames */
 #define MF_DEVICE_PTR 2   /* the pointer is device memory (HIP) */
@@ -105,7 +109,7 @@ typedef struct mf_stream_cfg {
   int32_t result_frames;        /* results (and maps) held until polled (0: 4L) */
   int32_t focus_mode;           /* MF_FOCUS_ACCEL (Eq. 3, the paper's) or MF_FOCUS_VELOCITY (Eq. 2) */
   int32_t diff_stride;          /* frames between the differenced centres, 1..64 (0: 1, the paper's) */
-  int32_t reserved;
+  int32_t map_mode;             /* MF_MAP_MAX or MF_MAP_SUM: the map normaliser Z of Eq. 7 */
 } mf_stream_cfg;
 
 /* One emitted frame.  valid bit 0: focus point defined (t >= 2 s, or t >= s for velocity;
@@ -118,7 +122,8 @@ typedef struct mf_focus {
   double T_w2c[16];         /* chained world-to-camera pose */
   float pose9[9];           /* raw head output (t3, quaternion xyzw, fov2); zeros for pushed poses */
   int32_t peak_x, peak_y;   /* argmax of the map (ties: smallest y*W + x) */
-  float reserved;
+  float sigma_px;           /* this frame's own Gaussian spread of Eq. 7 in pixels,
+                               clip(sigma * s, sigma_min, sigma_max); 0 without a focus point */
   double a_world[3];        /* Eq. 3 */
   double a_cam[3];          /* Eq. 4 */
   double u, v;              /* Eq. 6 */
@@ -139,23 +144,28 @@ typedef struct mf_stats {
   double gpu_ms;            /* device time of all batches (HIP events) */
 } mf_stats;
 
-/* Create an engine: copies the fp32 weight blob (caller keeps ownership) to the device,
+/* Sec. 2.2 (the per-window pose inference of the foundation model; here the seeded ViT whose sizes
+ * the workloads fix).  Create an engine: copies the fp32 weight blob (caller keeps ownership) to the device,
  * allocates the per-batch workspace, creates the stream and (threaded) the scheduler.
  * Blob order: W_p[588,D] b_p c_ref c_other, per layer {ln1.g ln1.b W_qkv[D,3D] b_qkv W_o b_o
  * ln2.g ln2.b W_1[D,F] b_1 W_2[F,D] b_2}, lnf.g lnf.b H_1[D,D] h_1 H_2[D,9] h_2;
  * linear layers stored [in, out].  n_floats must match exactly (MF_EINVAL otherwise). */
 mf_status mf_engine_create(const mf_model_cfg* model, const float* weights, size_t n_floats,
                            const mf_runtime_cfg* rt, mf_engine** out);
-/* Stop the scheduler, free every device allocation.  Safe on NULL. */
+/* Stop the scheduler, free every device allocation.  Safe on NULL.  (Resource management of the
+ * boundary; no paper passage.) */
 void mf_engine_destroy(mf_engine* e);
 
-/* Admit a stream.  MF_EAGAIN: the HBM budget is held by other streams now;
- * MF_ENOMEM: it can never fit; MF_EINVAL: bad sizes. */
+/* Admit a stream: the video {I_t} of Sec. 2.2 with its window L and overlap O (Sec. 2.2), the
+ * intrinsics K of Eq. 5, and the map's N, sigma and normaliser (Eq. 7).  MF_EAGAIN: the HBM budget
+ * is held by other streams now; MF_ENOMEM: it can never fit; MF_EINVAL: bad sizes or modes.
+ * cfg is copied; stream_id receives the new id. */
 mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream_id);
 
-/* Append n frames [n][3][H][W] (host or, with MF_DEVICE_PTR, device memory).  The frames
- * are copied before return.  MF_EAGAIN: the frame ring is full (poll, then retry);
- * MF_ECLOSED after end of stream. */
+/* Sec. 2.2: append frames of the stream {I_t}; a window of L frames runs once all of them are
+ * here.  n frames [n][3][H][W] (host or, with MF_DEVICE_PTR, device memory) are copied before
+ * return, so the caller may reuse rgb.  MF_EAGAIN: the frame ring is full (poll, then retry);
+ * MF_ECLOSED after end of stream; MF_EINVAL on a stream that takes poses. */
 mf_status mf_push_frames(mf_engine* e, int32_t stream_id, const float* rgb, int32_t n, int32_t flags);
 
 /* The "any pose estimator" entry (Sec. 1, Sec. 2.3): push poses instead of frames.
@@ -167,22 +177,29 @@ mf_status mf_push_frames(mf_engine* e, int32_t stream_id, const float* rgb, int3
 mf_status mf_push_poses(mf_engine* e, int32_t stream_id, const double* T_w2c, int32_t n,
                         int64_t first_frame, int32_t flags);
 
-/* Copy up to cap completed frames, in frame order, each exactly once.  maps (nullable):
+/* Sec. 2.2 (each frame emitted once, by the first window that completes it, in order), Eq. 1-6
+ * (the record's pose, motion vector and focus (u, v)) and Eq. 7 (the map).
+ * Copy up to cap completed frames, in frame order, each exactly once.  maps (nullable):
  * [cap][H][W] fp32 host memory, or device memory with MF_DEVICE_PTR in maps_flags.
  * MF_EAGAIN: nothing ready now; MF_ECLOSED: closed and fully drained (the id is released). */
 mf_status mf_poll_focus(mf_engine* e, int32_t stream_id, mf_focus* out, int32_t cap,
                         int32_t* n_out, float* maps, int32_t maps_flags);
 
-/* End of stream: no more pushes; the tail window is scheduled; results stay pollable. */
+/* End of stream (Sec. 2.2's windows, with this library's tail window [N - L, N) for frames the
+ * regular windows left out): no more pushes; the tail window is scheduled; results stay pollable. */
 mf_status mf_close_stream(mf_engine* e, int32_t stream_id);
 
-/* Non-threaded engines: run one batch of ready windows (n_windows may be NULL).
+/* Sec. 2.2's sliding-batch inference, several streams' ready windows fused into one batch.
+ * Non-threaded engines: run one batch of ready windows (n_windows may be NULL).
  * Threaded engines: MF_EINVAL. */
 mf_status mf_engine_step(mf_engine* e, int32_t* n_windows);
-/* Block until every ready window has been run and its results are pollable. */
+/* Block until every ready window has been run and its results are pollable (Sec. 2.2's windows). */
 mf_status mf_engine_sync(mf_engine* e);
+/* Counters of the run (frames, windows, batches, HBM in use, device time); no paper passage. */
 mf_status mf_engine_stats(mf_engine* e, mf_stats* out);
 
+/* Error reporting of the boundary (no paper passage): the name of a status, and the thread-local
+ * message of the last failed call on this thread (never NULL). */
 const char* mf_status_str(mf_status s);
 const char* mf_last_error(void);
 

@@ -13,7 +13,7 @@ import numpy as np
 from . import _lib
 from ._lib import (FOCUS_DTYPE, MF_ANCHOR_SE3, MF_ANCHOR_YAW, MF_ANCHOR_YAW_SCALE, MF_FOCUS_ACCEL,
                    MF_FOCUS_VELOCITY, MF_BF16, MF_DEVICE_PTR, MF_EAGAIN, MF_ECLOSED,
-                   MF_EOS, MF_FP32, MF_OK, MF_POSES_LOCAL)
+                   MF_EOS, MF_FP32, MF_MAP_MAX, MF_MAP_SUM, MF_OK, MF_POSES_LOCAL)
 
 PRECISIONS = {"fp32": MF_FP32, "bf16": MF_BF16, "fp8": _lib.MF_FP8}
 
@@ -126,11 +126,11 @@ class Engine:
                     sigma: float = 1.0, sigma_min: float = 0.0, sigma_max: float = 0.0,
                     anchor_mode: int = MF_ANCHOR_YAW, emit_maps: bool = True, ring_frames: int = 0,
                     result_frames: int = 0, allow_again: bool = False, focus_mode: int = 0,
-                    diff_stride: int = 1) -> int:
+                    diff_stride: int = 1, map_mode: int = MF_MAP_MAX) -> int:
         fx, fy, cx, cy = K
         c = _lib.StreamCfg(height, width, window, overlap, fx, fy, cx, cy, n_points, anchor_mode, sigma,
                            sigma_min, sigma_max, 1 if emit_maps else 0, ring_frames, result_frames, focus_mode,
-                           diff_stride, 0)
+                           diff_stride, map_mode)
         sid = C.c_int32()
         st = self.lib.mf_open_stream(self.h, C.byref(c), C.byref(sid))
         if allow_again and st == MF_EAGAIN:

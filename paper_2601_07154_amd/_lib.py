@@ -18,6 +18,7 @@ MF_FP32, MF_BF16, MF_FP8 = 0, 1, 2
 MF_ANCHOR_YAW, MF_ANCHOR_SE3, MF_ANCHOR_YAW_SCALE = 0, 1, 2
 MF_FOCUS_ACCEL, MF_FOCUS_VELOCITY = 0, 1
 MF_EOS, MF_DEVICE_PTR, MF_POSES_LOCAL = 1, 2, 4
+MF_MAP_MAX, MF_MAP_SUM = 0, 1
 
 
 class ModelCfg(C.Structure):
@@ -42,13 +43,13 @@ class StreamCfg(C.Structure):
                 ("n_points", C.c_int32), ("anchor_mode", C.c_int32),
                 ("sigma", C.c_double), ("sigma_min", C.c_double), ("sigma_max", C.c_double),
                 ("emit_maps", C.c_int32), ("ring_frames", C.c_int32), ("result_frames", C.c_int32),
-                ("focus_mode", C.c_int32), ("diff_stride", C.c_int32), ("reserved", C.c_int32)]
+                ("focus_mode", C.c_int32), ("diff_stride", C.c_int32), ("map_mode", C.c_int32)]
 
 
 class Focus(C.Structure):
     _fields_ = [("frame", C.c_int64), ("window", C.c_int32), ("valid", C.c_int32),
                 ("T_w2c", C.c_double * 16), ("pose9", C.c_float * 9), ("peak_x", C.c_int32),
-                ("peak_y", C.c_int32), ("reserved", C.c_float), ("a_world", C.c_double * 3),
+                ("peak_y", C.c_int32), ("sigma_px", C.c_float), ("a_world", C.c_double * 3),
                 ("a_cam", C.c_double * 3), ("u", C.c_double), ("v", C.c_double), ("s", C.c_double),
                 ("t_push", C.c_double), ("t_ready", C.c_double), ("t_window", C.c_double),
                 ("t_batch", C.c_double)]
@@ -62,12 +63,13 @@ class Stats(C.Structure):
 
 
 FOCUS_DTYPE = np.dtype({
-    "names": ["frame", "window", "valid", "T_w2c", "pose9", "peak_x", "peak_y", "a_world", "a_cam",
+    "names": ["frame", "window", "valid", "T_w2c", "pose9", "peak_x", "peak_y", "sigma_px", "a_world", "a_cam",
               "u", "v", "s", "t_push", "t_ready", "t_window", "t_batch"],
-    "formats": ["<i8", "<i4", "<i4", ("<f8", (16,)), ("<f4", (9,)), "<i4", "<i4", ("<f8", (3,)),
+    "formats": ["<i8", "<i4", "<i4", ("<f8", (16,)), ("<f4", (9,)), "<i4", "<i4", "<f4", ("<f8", (3,)),
                 ("<f8", (3,)), "<f8", "<f8", "<f8", "<f8", "<f8", "<f8", "<f8"],
     "offsets": [Focus.frame.offset, Focus.window.offset, Focus.valid.offset, Focus.T_w2c.offset,
-                Focus.pose9.offset, Focus.peak_x.offset, Focus.peak_y.offset, Focus.a_world.offset,
+                Focus.pose9.offset, Focus.peak_x.offset, Focus.peak_y.offset, Focus.sigma_px.offset,
+                Focus.a_world.offset,
                 Focus.a_cam.offset, Focus.u.offset, Focus.v.offset, Focus.s.offset, Focus.t_push.offset,
                 Focus.t_ready.offset, Focus.t_window.offset, Focus.t_batch.offset],
     "itemsize": C.sizeof(Focus),

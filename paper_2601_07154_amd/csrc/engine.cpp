@@ -70,6 +70,7 @@ struct Engine {
   std::unique_ptr<Executor> ex;
   mf_model_cfg model{};
   mf_runtime_cfg rt{};
+  std::mutex run_mu;            // one batch at a time (mf_engine_step / mf_engine_sync may race)
   std::mutex mu;
   std::condition_variable cv;
   std::map<int32_t, std::shared_ptr<Stream>> streams;
@@ -154,6 +155,7 @@ static bool work_ready_locked(Engine& e) {
 // Gather ready windows of every stream (round robin from the cursor) up to the token budget,
 // run them as one batch and hand the results to the streams.  Returns windows run, or < 0.
 static int step(Engine& e) {
+  std::lock_guard<std::mutex> run(e.run_mu);
   Batch b;
   std::vector<std::vector<double>> pose_store;
   std::vector<int> pose_idx;   // per batch window: index into pose_store or -1
@@ -419,6 +421,10 @@ mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream
   }
   if (c.focus_mode != MF_FOCUS_ACCEL && c.focus_mode != MF_FOCUS_VELOCITY) {
     set_err("unknown focus mode %d", c.focus_mode);
+    return MF_EINVAL;
+  }
+  if (c.map_mode != MF_MAP_MAX && c.map_mode != MF_MAP_SUM) {
+    set_err("unknown map mode %d", c.map_mode);
     return MF_EINVAL;
   }
   if (c.diff_stride == 0) c.diff_stride = 1;

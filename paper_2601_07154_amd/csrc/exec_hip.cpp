@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,7 @@ struct Plan {                      // host-side tables of one batch
   std::vector<int32_t> cam_rows;
   int64_t mtot = 0;
   int max_npad = 0;
+  int max_rows = 0;                // token rows of the largest window
 };
 
 class HipExecutor : public Executor {
@@ -159,6 +161,7 @@ class HipExecutor : public Executor {
 
   mf_status run_batch(const Batch& b, std::vector<mf_focus>& out, double* gpu_ms, std::string& err) override {
     HIPCHECK(hipSetDevice(device_));
+    latch_profiling();
     // ---- plan the forward part
     Plan p;
     std::vector<int32_t> loc_off(b.wins.size(), -1);
@@ -194,6 +197,7 @@ class HipExecutor : public Executor {
         sd.anchor_mode = w.cfg->anchor_mode;
         sd.focus_mode = w.cfg->focus_mode;
         sd.stride = w.cfg->diff_stride > 0 ? w.cfg->diff_stride : 1;
+        sd.map_mode = w.cfg->map_mode;
         sd.H = w.cfg->height; sd.W = w.cfg->width;
         sd.map_cap = w.res->map_cap;
         sd.maps = (float*)w.res->maps;
@@ -222,6 +226,10 @@ class HipExecutor : public Executor {
       out_n += (int32_t)(w.emit_end - w.emit_begin);
     }
     if (out_n > fcap_ || (int64_t)jobs.size() > fcap_) { err = "batch emits more frames than the workspace holds"; return MF_EINVAL; }
+    if (!jobs.empty()) {
+      const mf_status rp = ensure_psum((size_t)jobs.size() * map_row_blocks(max_h), err);
+      if (rp != MF_OK) return rp;
+    }
 
     // ---- pack every table into one pinned buffer, one upload
     size_t off = 0;
@@ -272,18 +280,20 @@ class HipExecutor : public Executor {
       HIPCHECK(chain_focus((const ChainGroup*)T(o_groups), (int)groups.size(), (const ChainWin*)T(o_cwins),
                            (const StreamDev*)T(o_sdev), tloc_, pose9_, res_, st_));
       HIPCHECK(focus_maps((const MapJob*)T(o_jobs), (int)jobs.size(), max_h, max_w, (const StreamDev*)T(o_sdev),
-                          res_, keys_, st_));
+                          res_, keys_, psum_, st_));
       HIPCHECK(hipMemcpyAsync(res_host_, res_, (size_t)out_n * sizeof(mf_focus), hipMemcpyDeviceToHost, st_));
       return MF_OK;
     };
     HIPCHECK(hipEventRecord(ev0_, st_));
     // per-kernel timing brackets launches with events on the stream: profiled batches run eagerly
-    if (use_graphs_ && !profiling_) {
-      // every kernel argument and copy size follows from these counts (table offsets included)
+    if (use_graphs_ && !prof_batch_) {
+      // Every kernel argument and copy size follows from these counts (table offsets included):
+      // the token rows, the frames and work lists, the windows and the largest of them (the fp8
+      // window quantiser's grid), the chain and map tables, the poses and the records.
       char sig[256];
-      snprintf(sig, sizeof sig, "%lld/%d/%zu/%zu/%zu/%zu/%zu/%zu/%d/%d/%d/%d/%d/%zu/%d", (long long)p.mtot,
-               p.max_npad, p.frames.size(), p.fwork.size(), p.gwork.size(), groups.size(), cwins.size(), jobs.size(),
-               max_h, max_w, pose_rows, fwd_frames, out_n, off, profiling_ ? 1 : 0);
+      snprintf(sig, sizeof sig, "%lld/%d/%zu/%zu/%zu/%zu/%d/%zu/%zu/%zu/%d/%d/%d/%d/%d/%zu", (long long)p.mtot,
+               p.max_npad, p.frames.size(), p.fwork.size(), p.gwork.size(), p.gsegs.size(), p.max_rows,
+               groups.size(), cwins.size(), jobs.size(), max_h, max_w, pose_rows, fwd_frames, out_n, off);
       auto it = graphs_.find(sig);
       if (it == graphs_.end()) {
         if (graphs_.size() >= 64) clear_graphs();
@@ -330,6 +340,7 @@ class HipExecutor : public Executor {
   mf_status forward_frames(const float* frames_dev, int S, int H, int W, float* pose9_host, double* T_host,
                            int max_layers, float* tokens_host, std::string& err) override {
     HIPCHECK(hipSetDevice(device_));
+    latch_profiling();
     if (S < 1 || H % 14 || W % 14 || H <= 0 || W <= 0) { err = "bad frame geometry"; return MF_EINVAL; }
     StreamRes r;
     r.ring = (void*)frames_dev;
@@ -392,6 +403,9 @@ class HipExecutor : public Executor {
   }
 
   void profile(double* ag_ms, int64_t* ag_calls, double* af_ms, double* g_ms, int enable) override {
+    // may run on an API thread while the scheduler thread runs a batch: the switch and the sums are
+    // shared under prof_mu_, and a batch reads the switch once, when it starts (latch_profiling)
+    std::lock_guard<std::mutex> lk(prof_mu_);
     if (ag_ms) *ag_ms = prof_ag_ms_;
     if (ag_calls) *ag_calls = prof_ag_calls_;
     if (af_ms) *af_ms = prof_af_ms_;
@@ -537,8 +551,22 @@ class HipExecutor : public Executor {
     return MF_OK;
   }
 
+  // Partial sums of the map normaliser: one double per map job and render workgroup.  Grown before
+  // a batch is captured or launched; a new buffer invalidates captured graphs.
+  mf_status ensure_psum(size_t n, std::string& err) {
+    if (n <= psum_cap_) return MF_OK;
+    clear_graphs();
+    dfree(psum_);
+    psum_ = nullptr;
+    psum_cap_ = std::max<size_t>(n, (size_t)fcap_ * 64);
+    HIPCHECK(dmalloc(&psum_, psum_cap_ * sizeof(double)));
+    return MF_OK;
+  }
+
   // Position-code rows for a (gh, gw) grid: one table per resolution in a shared arena.
+  // Opens of several streams may run at once on API threads (and a forward on the scheduler thread).
   mf_status pe_rows_for(int gh, int gw, int* base, std::string& err) {
+    std::lock_guard<std::mutex> lk(pe_mu_);
     auto key = std::make_pair(gh, gw);
     auto it = pe_index_.find(key);
     if (it != pe_index_.end()) { *base = it->second; return MF_OK; }
@@ -581,6 +609,7 @@ class HipExecutor : public Executor {
     for (int q0 = 0; q0 < w.size * npad; q0 += qt_) p.gwork.push_back({gi, q0});
     p.mtot += (int64_t)w.size * npad;
     p.max_npad = std::max(p.max_npad, npad);
+    p.max_rows = std::max(p.max_rows, w.size * npad);
   }
 
   // ------------------------------------------------------------------ the network
@@ -596,10 +625,8 @@ class HipExecutor : public Executor {
     HIPCHECK(run_gemm(EPI_PATCH, g));
     // fp8: activations feeding the QKV and MLP GEMMs are quantised per window (dynamic scales)
     const int nwin = (int)p.gsegs.size();
-    int max_rows = 0;
-    for (const AttnSeg& w : p.gsegs) max_rows = std::max(max_rows, w.nf * w.npad);
     auto quant = [&](const void* y, int C, unsigned char* q, float* srow) {
-      return window_quant_fp8((const __bf16*)y, C, gsegs, nwin, max_rows, amax_, q, srow, st_);
+      return window_quant_fp8((const __bf16*)y, C, gsegs, nwin, p.max_rows, amax_, q, srow, st_);
     };
     for (int l = 0; l < layers; ++l) {
       const LayerW& L = layers_[l];
@@ -670,8 +697,12 @@ class HipExecutor : public Executor {
   struct ProfEv { hipEvent_t a, b; int kind; };
   std::vector<ProfEv> prof_pool_;
   size_t prof_used_ = 0;
+  void latch_profiling() {
+    std::lock_guard<std::mutex> lk(prof_mu_);
+    prof_batch_ = profiling_;
+  }
   void prof_begin() {
-    if (!profiling_) return;
+    if (!prof_batch_) return;
     if (prof_target_) {   // capturing: the graph owns its events
       ProfEv e;
       hipEventCreate(&e.a);
@@ -690,7 +721,7 @@ class HipExecutor : public Executor {
     hipEventRecord(prof_pool_[prof_used_].a, st_);
   }
   void prof_end(int kind) {
-    if (!profiling_) return;
+    if (!prof_batch_) return;
     if (prof_target_) {
       prof_target_->back().kind = kind;
       hipEventRecord(prof_target_->back().b, st_);
@@ -709,9 +740,10 @@ class HipExecutor : public Executor {
     else prof_gemm_ms_ += ms;
   }
   void collect_profile(std::string&) {
+    std::lock_guard<std::mutex> lk(prof_mu_);
     for (size_t i = 0; i < prof_used_; ++i) account(prof_pool_[i]);
     prof_used_ = 0;
-    if (replayed_prof_ && profiling_)
+    if (replayed_prof_ && prof_batch_)
       for (const ProfEv& e : *replayed_prof_) account(e);
     replayed_prof_ = nullptr;
   }
@@ -724,7 +756,7 @@ class HipExecutor : public Executor {
     for (auto& L : layers_) { F(L.Wqkv); F(L.Wo); F(L.W1); F(L.W2); }
     F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(Q_); F(K_); F(Vt_);
     F(Y8_); F(H8_); F(srow_); F(srow2_); F(amax_); F(wscale_); F(wamax_);
-    F(camln_); F(camg_); F(pose9_); F(tloc_); F(res_); F(keys_); F(pe_); F(tab_dev_);
+    F(camln_); F(camg_); F(pose9_); F(tloc_); F(res_); F(keys_); F(psum_); F(pe_); F(tab_dev_);
     if (res_host_) hipHostFree(res_host_);
     if (tab_host_) hipHostFree(tab_host_);
     for (auto& e : prof_pool_) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
@@ -779,14 +811,19 @@ class HipExecutor : public Executor {
   mf_focus* res_ = nullptr;
   mf_focus* res_host_ = nullptr;
   unsigned long long* keys_ = nullptr;
+  double* psum_ = nullptr;
+  size_t psum_cap_ = 0;
   char* tab_dev_ = nullptr;
   char* tab_host_ = nullptr;
   size_t tab_cap_ = 0;
   float* pe_ = nullptr;
   int pe_rows_ = 0, pe_cap_ = 0;
   std::map<std::pair<int, int>, int> pe_index_;
+  std::mutex pe_mu_;           // pe_, pe_rows_ and pe_index_
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
-  bool profiling_ = false;
+  std::mutex prof_mu_;         // profiling_ and the prof_*_ sums (mf_profile runs on API threads)
+  bool profiling_ = false;     // the switch set by mf_profile
+  bool prof_batch_ = false;    // the switch as the running batch read it when it started
   bool use_graphs_ = false;
   bool fp8_ = false;
   unsigned char *Y8_ = nullptr, *H8_ = nullptr;

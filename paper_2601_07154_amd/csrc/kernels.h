@@ -100,6 +100,8 @@ struct StreamDev {            // per-stream constants of one batch
   int32_t anchor_mode, H, W, map_cap;
   float* maps;                // map ring [map_cap][H][W]
   int32_t focus_mode, stride; // MF_FOCUS_ACCEL / MF_FOCUS_VELOCITY, difference stride s
+  int32_t map_mode;           // MF_MAP_MAX / MF_MAP_SUM: the normaliser Z of Eq. 7
+  int32_t pad;
 };
 
 enum ChainMode { CHAIN_ANCHOR = 0, CHAIN_FIRST = 1, CHAIN_WORLD = 2 };
@@ -117,8 +119,12 @@ struct MapJob { int32_t stream, out; int64_t frame; };
 hipError_t chain_focus(const ChainGroup* groups, int ngroups, const ChainWin* wins,
                        const StreamDev* streams, const double* T_loc, const float* pose9,
                        mf_focus* out, hipStream_t s);
-// keys: [njobs] scratch (cleared here).  Renders every job's map into its stream's ring.
+// Rows of the map one render workgroup covers; the sum normaliser takes one partial per workgroup.
+constexpr int MAP_ROWS = 8;
+inline int map_row_blocks(int max_h) { return (max_h + MAP_ROWS - 1) / MAP_ROWS; }
+// keys: [njobs] scratch (cleared here); psum: [njobs][map_row_blocks(max_h)] scratch (every entry
+// written before it is read).  Renders every job's map into its stream's ring.
 hipError_t focus_maps(const MapJob* jobs, int njobs, int max_h, int max_w, const StreamDev* streams,
-                      mf_focus* out, unsigned long long* keys, hipStream_t s);
+                      mf_focus* out, unsigned long long* keys, double* psum, hipStream_t s);
 
 }  // namespace mf

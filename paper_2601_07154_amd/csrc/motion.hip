@@ -9,7 +9,8 @@
 //
 // focus_maps: per emitted frame, the last N valid accelerations rotated by the frame's
 // rotation and projected are the Gaussian centres; spread clip(sigma |a_w,i|); the map is
-// normalised by its maximum (zero map below 1e-30).
+// normalised by its maximum, or by its sum over the pixel grid (MF_MAP_SUM); zero map when the
+// normaliser is below 1e-30.
 #include "device.h"
 #include "kernels.h"
 
@@ -136,7 +137,6 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
         r.pose9[i] = w.has_pose9 ? pose9[(int64_t)(w.loc_off + (t - w.start)) * 9 + i] : 0.0f;
       r.peak_x = -1;
       r.peak_y = -1;
-      r.reserved = 0.0f;
       double aw[3] = {0.0, 0.0, 0.0}, ac[3] = {0.0, 0.0, 0.0}, u = 0.0, v = 0.0, s = 0.0;
       int valid = 0;
       const int ds = sd.stride;
@@ -164,6 +164,7 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
       }
       h.s = s;
       h.valid = valid;
+      r.sigma_px = valid ? (float)fmin(fmax(sd.sigma * s, sd.sigma_min), sd.sigma_max) : 0.0f;
       r.s = s;
       r.u = u;
       r.v = v;
@@ -187,7 +188,6 @@ hipError_t chain_focus(const ChainGroup* groups, int ngroups, const ChainWin* wi
 }
 
 // ------------------------------------------------------------------ focus maps
-constexpr int MAP_ROWS = 8;       // rows per workgroup
 constexpr int MAX_POINTS = 32;
 
 __global__ void clear_keys_kernel(unsigned long long* keys, int n) {
@@ -196,17 +196,24 @@ __global__ void clear_keys_kernel(unsigned long long* keys, int n) {
 }
 
 // Unnormalised map G of job blockIdx.y, rows blockIdx.x*8 .., plus the running max key
-// (G bits << 32 | ~index) so the maximum and its smallest index come out of one atomic.
+// (G bits << 32 | ~index) so the maximum and its smallest index come out of one atomic, and the
+// workgroup's partial sum of G (summed in double in a fixed order: the normaliser is the same
+// whatever else shares the launch).
 __global__ __launch_bounds__(256) void map_render_kernel(const MapJob* __restrict__ jobs,
                                                          const StreamDev* __restrict__ streams,
-                                                         unsigned long long* __restrict__ keys) {
+                                                         unsigned long long* __restrict__ keys,
+                                                         double* __restrict__ psum) {
   __shared__ double pu[MAX_POINTS], pv[MAX_POINTS], pk[MAX_POINTS];
   __shared__ int pok[MAX_POINTS];
   __shared__ unsigned long long red[4];
+  __shared__ double sred[4];
   const MapJob job = jobs[blockIdx.y];
   const StreamDev sd = streams[job.stream];
   const int y0 = blockIdx.x * MAP_ROWS;
-  if (y0 >= sd.H) return;
+  if (y0 >= sd.H) {   // rows beyond this stream's frame: nothing to render, a zero partial sum
+    if (threadIdx.x == 0) psum[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
   const int tid = threadIdx.x;
   const int N = sd.n_points;
   const FrameHist* hist = sd.hist;
@@ -234,6 +241,7 @@ __global__ __launch_bounds__(256) void map_render_kernel(const MapJob* __restric
   __syncthreads();
   float* G = sd.maps + (int64_t)(job.frame % sd.map_cap) * sd.H * sd.W;
   unsigned long long best = 0ull;
+  double part = 0.0;
   const int y1 = min(y0 + MAP_ROWS, sd.H);
   for (int idx = tid; idx < (y1 - y0) * sd.W; idx += 256) {
     const int y = y0 + idx / sd.W, x = idx - (idx / sd.W) * sd.W;
@@ -245,6 +253,7 @@ __global__ __launch_bounds__(256) void map_render_kernel(const MapJob* __restric
     }
     const int64_t pix = (int64_t)y * sd.W + x;
     G[pix] = acc;
+    part += (double)acc;
     const unsigned long long key = ((unsigned long long)__float_as_uint(acc) << 32) |
                                    (unsigned long long)(0xFFFFFFFFu - (unsigned)pix);
     best = key > best ? key : best;
@@ -252,29 +261,46 @@ __global__ __launch_bounds__(256) void map_render_kernel(const MapJob* __restric
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned long long other = __shfl_xor(best, o, 64);
     best = other > best ? other : best;
+    part += __shfl_xor(part, o, 64);
   }
-  if ((tid & 63) == 0) red[tid >> 6] = best;
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = best;
+    sred[tid >> 6] = part;
+  }
   __syncthreads();
   if (tid == 0) {
     for (int w = 1; w < 4; ++w) best = red[w] > best ? red[w] : best;
     best = red[0] > best ? red[0] : best;
     atomicMax(&keys[blockIdx.y], best);
+    psum[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ((sred[0] + sred[1]) + sred[2]) + sred[3];
   }
 }
 
 __global__ __launch_bounds__(256) void map_normalise_kernel(const MapJob* __restrict__ jobs,
                                                             const StreamDev* __restrict__ streams,
                                                             const unsigned long long* __restrict__ keys,
+                                                            const double* __restrict__ psum, int nrb,
                                                             mf_focus* __restrict__ out) {
   const MapJob job = jobs[blockIdx.y];
   const StreamDev sd = streams[job.stream];
   const unsigned long long key = keys[blockIdx.y];
-  const float Z = __uint_as_float((unsigned)(key >> 32));
-  const bool zero = !(Z >= 1e-30f);
+  const float zmax = __uint_as_float((unsigned)(key >> 32));
   float* G = sd.maps + (int64_t)(job.frame % sd.map_cap) * sd.H * sd.W;
   const int64_t npix = (int64_t)sd.H * sd.W;
-  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < npix; p += (int64_t)gridDim.x * 256)
-    G[p] = zero ? 0.0f : G[p] / Z;
+  bool zero;
+  if (sd.map_mode == MF_MAP_SUM) {
+    // the render workgroups' partial sums, added in their row order by every workgroup alike
+    double Z = 0.0;
+    for (int b = 0; b < nrb; ++b) Z += psum[(int64_t)blockIdx.y * nrb + b];
+    zero = !(Z >= 1e-30);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < npix; p += (int64_t)gridDim.x * 256)
+      G[p] = zero ? 0.0f : (float)((double)G[p] / Z);
+  } else {
+    zero = !(zmax >= 1e-30f);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < npix; p += (int64_t)gridDim.x * 256)
+      G[p] = zero ? 0.0f : G[p] / zmax;
+  }
+  // the argmax is the same under both normalisers (the largest G, ties to the smallest index)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     mf_focus& r = out[job.out];
     if (zero) {
@@ -290,13 +316,14 @@ __global__ __launch_bounds__(256) void map_normalise_kernel(const MapJob* __rest
 }
 
 hipError_t focus_maps(const MapJob* jobs, int njobs, int max_h, int max_w, const StreamDev* streams,
-                      mf_focus* out, unsigned long long* keys, hipStream_t s) {
+                      mf_focus* out, unsigned long long* keys, double* psum, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
+  const int nrb = map_row_blocks(max_h);
   hipLaunchKernelGGL(clear_keys_kernel, dim3((njobs + 255) / 256), dim3(256), 0, s, keys, njobs);
-  hipLaunchKernelGGL(map_render_kernel, dim3((max_h + MAP_ROWS - 1) / MAP_ROWS, njobs), dim3(256), 0, s,
-                     jobs, streams, keys);
+  hipLaunchKernelGGL(map_render_kernel, dim3(nrb, njobs), dim3(256), 0, s, jobs, streams, keys, psum);
   const int chunks = (int)(((int64_t)max_h * max_w + 256 * 8 - 1) / (256 * 8));
-  hipLaunchKernelGGL(map_normalise_kernel, dim3(chunks, njobs), dim3(256), 0, s, jobs, streams, keys, out);
+  hipLaunchKernelGGL(map_normalise_kernel, dim3(chunks, njobs), dim3(256), 0, s, jobs, streams, keys, psum, nrb,
+                     out);
   return hipGetLastError();
 }
 

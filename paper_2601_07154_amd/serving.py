@@ -6,9 +6,13 @@ their capture rate (or all at once in the throughput regime), and results are po
 engine's scheduler thread completes windows.  Every window that is ready when a batch starts
 joins that batch, whatever stream it belongs to.
 
-Reported per frame: latency = t_ready - t_push, split into buffering (t_window - t_push: waiting
-for the window's last frame, or the end of the stream for a tail window), queueing (t_batch -
-t_window: waiting for a batch to start) and compute (t_ready - t_batch: the batch itself).
+Reported per frame, in the paced regime: latency from the frame's capture time (the stream's
+arrival + i / fps) to its result, split into admission (capture to push: waiting for the stream to
+be admitted under the HBM budget, or for room in its frame ring), buffering (t_window - t_push:
+waiting for the window's last frame, or the end of the stream for a tail window), queueing (t_batch -
+t_window: waiting for a batch to start) and compute (t_ready - t_batch: the batch itself).  In the
+throughput regime every frame is available at its stream's arrival and the run measures frames/s;
+its latency is counted from the push (t_ready - t_push).
 """
 from __future__ import annotations
 
@@ -37,6 +41,7 @@ class StreamState:
     done: bool = False
     admitted_at: float = -1.0
     records: list = field(default_factory=list)
+    wait: list = field(default_factory=list)   # per pushed frame: push time - capture time (s)
 
 
 def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float = 30.0,
@@ -69,12 +74,13 @@ def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float
             st.admitted_at = now
             active.append(st)
             pending.pop(0)
-        # pushes: frames whose capture time has come (paced) or everything (throughput regime)
+        # pushes: frames whose capture time (arrival + i / fps) has come (paced), or everything
+        # (throughput regime)
         for st in active:
             s = st.spec
             if st.pushed >= s.length:
                 continue
-            due = s.length if not paced else min(s.length, int((now - st.admitted_at) * fps) + 1)
+            due = s.length if not paced else min(s.length, int((now - s.arrival) * fps) + 1)
             key = (s.height, s.width)
             if key not in pools:
                 pools[key] = frame_pool(s.height, s.width)
@@ -85,6 +91,9 @@ def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float
                 rc = engine.push_frames(st.sid, pool[off:off + n], eos=st.pushed + n == s.length, allow_again=True)
                 if rc == MF_EAGAIN:
                     break
+                t_pushed = time.perf_counter() - t0
+                for i in range(st.pushed, st.pushed + n):
+                    st.wait.append(max(0.0, t_pushed - (s.arrival + i / fps)) if paced else 0.0)
                 st.pushed += n
         if not getattr(engine, "threaded", True):
             engine.step()
@@ -104,20 +113,30 @@ def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float
             time.sleep(0.001)
     wall = time.perf_counter() - t0
     recs = [np.concatenate(st.records) if st.records else np.zeros(0) for st in states]
-    return dict(records=recs, wall=wall, stats=engine.stats(), states=states)
+    waits = [np.asarray(st.wait, dtype=np.float64) for st in states]
+    return dict(records=recs, waits=waits, wall=wall, stats=engine.stats(), states=states)
 
 
-def latency_summary(recs_list):
-    """p50 / p99 / mean per-frame latency in ms, and the same for its buffering, queueing and
-    compute parts."""
-    recs = [r for r in recs_list if len(r)]
+def latency_summary(recs_list, waits=None):
+    """p50 / p99 / mean per-frame latency in ms, and the same for its parts: admission (capture to
+    push, when waits [per stream, per frame, seconds] is given), buffering, queueing and compute.
+    With waits the latency counts from each frame's capture time, else from its push."""
+    pairs = [(r, None if waits is None else waits[i]) for i, r in enumerate(recs_list) if len(r)]
+    recs = [r for r, _ in pairs]
     cat = lambda f: np.concatenate([f(r) for r in recs]) * 1e3
-    lat = cat(lambda r: r["t_ready"] - r["t_push"])
+    adm = (np.concatenate([w[r["frame"]] for r, w in pairs]) * 1e3 if waits is not None
+           else np.zeros(sum(len(r) for r in recs)))
+    lat = cat(lambda r: r["t_ready"] - r["t_push"]) + adm
     out = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-           "mean_ms": float(lat.mean()), "frames": int(lat.size)}
-    for name, f in (("buffering", lambda r: r["t_window"] - r["t_push"]),
-                    ("queueing", lambda r: r["t_batch"] - r["t_window"]),
-                    ("compute", lambda r: r["t_ready"] - r["t_batch"])):
+           "mean_ms": float(lat.mean()), "frames": int(lat.size),
+           "from": "capture" if waits is not None else "push"}
+    parts = [("buffering", lambda r: r["t_window"] - r["t_push"]),
+             ("queueing", lambda r: r["t_batch"] - r["t_window"]),
+             ("compute", lambda r: r["t_ready"] - r["t_batch"])]
+    if waits is not None:
+        out["admission"] = {"p50_ms": float(np.percentile(adm, 50)), "p99_ms": float(np.percentile(adm, 99)),
+                            "mean_ms": float(adm.mean())}
+    for name, f in parts:
         part = cat(f)
         out[name] = {"p50_ms": float(np.percentile(part, 50)), "p99_ms": float(np.percentile(part, 99)),
                      "mean_ms": float(part.mean())}

@@ -5,6 +5,8 @@
 //   pose9[2] = batch ordinal, pose9[3] = frames of the same stream in that batch.
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -32,8 +34,22 @@ class StubExecutor : public Executor {
     const uint64_t hw = (uint64_t)c.height * c.width;
     return (uint64_t)ring_cap * 3 * hw * 4 + (uint64_t)map_cap * hw * 4 + (uint64_t)hist_n * 168;
   }
-  mf_status open_stream(const mf_stream_cfg&, StreamRes* r, std::string&) override {
+  // Shared state as the device executor has it: a per-resolution table that stream opens extend
+  // (opens run on API threads, outside the engine lock) and a profiling switch that API threads
+  // flip while the scheduler thread runs batches.  The locks mirror the device executor's, so the
+  // race test exercises the same discipline.
+  mf_status open_stream(const mf_stream_cfg& c, StreamRes* r, std::string&) override {
     r->ring = (void*)0x1;
+    std::lock_guard<std::mutex> lk(pe_mu_);
+    auto key = std::make_pair(c.height / 14, c.width / 14);
+    auto it = pe_index_.find(key);
+    if (it == pe_index_.end()) {
+      pe_index_[key] = pe_rows_;
+      r->pe_base = pe_rows_;
+      pe_rows_ += key.first * key.second;
+    } else {
+      r->pe_base = it->second;
+    }
     return MF_OK;
   }
   void close_stream(StreamRes* r) override { r->ring = nullptr; }
@@ -41,6 +57,11 @@ class StubExecutor : public Executor {
     return MF_OK;
   }
   mf_status run_batch(const Batch& b, std::vector<mf_focus>& out, double* ms, std::string&) override {
+    bool prof;
+    {
+      std::lock_guard<std::mutex> lk(prof_mu_);
+      prof = profiling_;
+    }
     ++batches_;
     for (const BatchWindow& w : b.wins) {
       int same = 0;
@@ -62,6 +83,10 @@ class StubExecutor : public Executor {
       }
     }
     if (ms) *ms = 0.0;
+    if (prof) {
+      std::lock_guard<std::mutex> lk(prof_mu_);
+      prof_batches_ += 1.0;
+    }
     return MF_OK;
   }
   mf_status copy_maps(const mf_stream_cfg& c, StreamRes*, int64_t frame, int n, float* dst, bool, std::string&) override {
@@ -78,12 +103,25 @@ class StubExecutor : public Executor {
     err = "no device";
     return MF_EDEVICE;
   }
-  void profile(double*, int64_t*, double*, double*, int) override {}
+  void profile(double* ag, int64_t* calls, double*, double*, int enable) override {
+    std::lock_guard<std::mutex> lk(prof_mu_);
+    if (ag) *ag = prof_batches_;
+    if (calls) *calls = 0;
+    if (enable >= 0) {
+      profiling_ = enable != 0;
+      prof_batches_ = 0.0;
+    }
+  }
 
  private:
   uint64_t budget_ = 0, fixed_ = 0;
   int64_t mcap_ = 0;
   int batches_ = 0;
+  std::mutex pe_mu_, prof_mu_;
+  std::map<std::pair<int, int>, int> pe_index_;
+  int pe_rows_ = 0;
+  bool profiling_ = false;
+  double prof_batches_ = 0.0;
 };
 
 Executor* make_executor() { return new StubExecutor(); }

@@ -8,15 +8,18 @@
 #include <vector>
 
 #include "mf.h"
+#include "mf_ops.h"
 
-static int run_stream(mf_engine* e, int n, int* bad) {
+#include <mutex>
+
+static int run_stream(mf_engine* e, int n, int res, int* bad) {
   mf_stream_cfg c;
   memset(&c, 0, sizeof c);
-  c.height = 28; c.width = 28; c.window = 8; c.overlap = 4;
+  c.height = 28 + 14 * res; c.width = 28; c.window = 8; c.overlap = 4;
   c.fx = c.fy = 50; c.cx = c.cy = 14; c.n_points = 15; c.sigma = 1.0; c.ring_frames = 16;
   int32_t sid;
   while (mf_open_stream(e, &c, &sid) == MF_EAGAIN) std::this_thread::yield();
-  std::vector<float> fr(3 * 28 * 28, 0.0f);
+  std::vector<float> fr(3 * c.height * c.width, 0.0f);
   int pushed = 0;
   int64_t next = 0;
   mf_focus out[32];
@@ -48,8 +51,29 @@ int main() {
   if (mf_engine_create(&m, &w, 1, &rt, &e) != MF_OK) { printf("create failed: %s\n", mf_last_error()); return 2; }
   int bad[6] = {0};
   std::vector<std::thread> th;
-  for (int i = 0; i < 6; ++i) th.emplace_back([&, i] { run_stream(e, 30 + 7 * i, &bad[i]); });
+  // streams of three resolutions opened from their own threads (the executor's per-resolution table
+  // grows concurrently), while another thread switches per-kernel profiling on and off
+  for (int i = 0; i < 6; ++i) th.emplace_back([&, i] { run_stream(e, 30 + 7 * i, i % 3, &bad[i]); });
+  bool stop = false;
+  std::mutex stop_mu;
+  std::thread prof([&] {
+    for (int k = 0;; ++k) {
+      {
+        std::lock_guard<std::mutex> lk(stop_mu);
+        if (stop) break;
+      }
+      double ms = 0.0;
+      int64_t calls = 0;
+      mf_profile(e, k & 1, &ms, &calls, nullptr, nullptr);
+      std::this_thread::yield();
+    }
+  });
   for (auto& t : th) t.join();
+  {
+    std::lock_guard<std::mutex> lk(stop_mu);
+    stop = true;
+  }
+  prof.join();
   mf_stats st;
   mf_engine_stats(e, &st);
   mf_engine_destroy(e);

@@ -26,12 +26,12 @@ def _drain(eng, sid, H, W, cap=4096):
 
 
 def _run_poses_engine(m, T, K, H, W, sigma, n_points=15, local_windows=None, focus_mode=0, diff_stride=1,
-                      anchor_mode=0):
+                      anchor_mode=0, map_mode=0):
     eng = m.Engine(1, 128, 4, 128, np.zeros(mf_synth.weight_count(mf_synth.ModelConfig(1, 128, 4, 128)),
                                             np.float32), precision="fp32", max_tokens=16384)
     n = len(T) if T is not None else sum(len(t) for _, t in local_windows)
     sid = eng.open_stream(H, W, 16, 8, K, n_points=n_points, sigma=sigma, result_frames=max(64, n),
-                          focus_mode=focus_mode, diff_stride=diff_stride, anchor_mode=anchor_mode)
+                          focus_mode=focus_mode, diff_stride=diff_stride, anchor_mode=anchor_mode, map_mode=map_mode)
     if local_windows is None:
         eng.push_poses(sid, T, 0, eos=True)
     else:
@@ -82,6 +82,33 @@ def test_world_poses_match_oracle_track_and_maps():
             assert r["valid"] & 2
             am = r["peak_y"] * W + r["peak_x"]
             assert ref["maps"][i].ravel()[am] >= 1.0 - 1e-5
+        else:
+            assert not (r["valid"] & 2) and not maps[i].any()
+
+
+def test_sum_normalised_maps_and_sigma_px_match_oracle():
+    """Eq. 7 with Z = the map's sum over the pixel grid (MF_MAP_SUM), and each record's own spread
+    sigma_px, against the oracle; a frame whose normaliser underflows gives the zero map in both."""
+    torch_cuda()
+    m = mf()
+    K = (400.0, 380.0, 252.0, 140.0)
+    H, W = 154, 266     # not a multiple of the render workgroup's 8 rows
+    path = mf_synth.CameraPath(velocity=(0.2, 0.0, 1.5), accel=(0.3, -0.1, 0.5), sway_deg=3.0)
+    T = path.poses(44)
+    sigma = 3e4
+    recs, maps = _run_poses_engine(m, T, K, H, W, sigma, map_mode=m.MF_MAP_SUM)
+    ref = pipeline.run_poses(T, K, H, W, sigma=sigma, map_mode=motion.MAP_SUM)
+    np.testing.assert_allclose(recs["sigma_px"], ref["sigma_px"], rtol=1e-6, atol=0)
+    assert (recs["sigma_px"][:2] == 0).all()
+    for i, r in enumerate(recs):
+        if ref["Z"][i] >= 1e-30:
+            # every value within 1e-5 of the map's peak (fp32 Gaussians, a double-precision sum)
+            np.testing.assert_allclose(maps[i], ref["maps"][i], atol=1e-5 * ref["maps"][i].max(), rtol=0)
+            assert abs(float(maps[i].astype(np.float64).sum()) - 1.0) < 1e-4
+            assert r["valid"] & 2
+            # the peak (fp32 values on the device): the oracle's map is maximal there up to fp32 rounding
+            am = r["peak_y"] * W + r["peak_x"]
+            assert ref["maps"][i].ravel()[am] >= ref["maps"][i].max() * (1.0 - 1e-5)
         else:
             assert not (r["valid"] & 2) and not maps[i].any()
 
@@ -230,6 +257,49 @@ def test_graph_replays_match_eager(precision):
         m.op_layernorm("fp32", x, y, torch.ones(384, device="cuda"), torch.zeros(384, device="cuda"))
         torch.cuda.synchronize()
     eng.close()
+
+
+def test_graph_key_separates_batches_with_equal_counts():
+    """Two batch compositions with the same token rows, frames and attention work items but different
+    windows (short streams of 14 + 10 frames, then of 16 + 8, at 720 patches per frame): the fp8
+    window quantiser's grid follows the largest window, so the second batch must not replay the
+    graph captured for the first.  Results equal the eager launch sequence bit for bit."""
+    torch = torch_cuda()
+    m = mf()
+    model = mf_synth.ModelConfig(2, 384, 6, 1536)
+    blob = mf_synth.make_weights(model, 4)
+    H, W, L, O = 280, 504, 16, 8
+    rows = m.rows_per_frame(H, W)
+    assert rows == 728
+    K = (400.0, 400.0, W / 2, H / 2)
+    frames = torch.from_numpy(mf_synth.make_frames(16, H, W, 21)).cuda()
+
+    def batch(eng, lengths):
+        sids = [eng.open_stream(H, W, L, O, K, sigma=300.0, ring_frames=L, result_frames=L) for _ in lengths]
+        for sid, n in zip(sids, lengths):
+            eng.push_frames(sid, frames[:n], eos=True)
+        eng.sync()
+        out = []
+        for sid, n in zip(sids, lengths):
+            mp = np.zeros((n, H, W), np.float32)
+            r, _ = eng.poll(sid, n, mp)
+            eng.poll(sid, 1)
+            out.append((r, mp))
+        return out
+
+    eager = m.Engine.from_model(model, blob, precision="fp8", max_tokens=24 * rows + 64, graphs=False)
+    ref = batch(eager, [16, 8])
+    eager.close()
+    eng = m.Engine.from_model(model, blob, precision="fp8", max_tokens=24 * rows + 64, graphs=True)
+    batch(eng, [14, 10])                 # captured first
+    got = batch(eng, [16, 8])
+    st = eng.stats()
+    eng.close()
+    assert st["batches_run"] == 2
+    for (r, mp), (rr, rmp) in zip(got, ref):
+        for f in ("T_w2c", "pose9", "a_world", "u", "v", "valid", "peak_x", "peak_y", "frame"):
+            np.testing.assert_array_equal(r[f], rr[f], err_msg=f)
+        np.testing.assert_array_equal(mp, rmp)
 
 
 @pytest.mark.parametrize("threaded", [False, True])
