@@ -79,6 +79,18 @@ mf_status mf_op_quantize_fp8(const float* x, int64_t n, float scale, void* q, vo
 mf_status mf_op_quantize_fp8_windows(const void* y, int32_t C, const int32_t* segs, int32_t nwin, void* q,
                                      float* srow, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mf_op_quantize_fp8_windows with the same arguments and
+ * results, calling no allocator.  Its window table and per-window amax counters live in a static
+ * device array of the library, one copy per GPU, held until the process ends
+ * (MF_NOALLOC_MAX_WINDOWS * 20 bytes); the counters are cleared on every call.  nwin above
+ * MF_NOALLOC_MAX_WINDOWS -> MF_EINVAL.  Every call on one GPU uses that GPU's array: calls that
+ * overlap on one GPU (other host threads or streams) race and must be serialised by the caller.
+ * Returns after the quantiser has finished on `stream`. */
+#define MF_NOALLOC_MAX_WINDOWS 4096
+mf_status mf_op_quantize_fp8_windows_noalloc(const void* y, int32_t C, const int32_t* segs, int32_t nwin,
+                                             void* q, float* srow, void* stream);
+
 /* y = LayerNorm(x) * g + b over rows of dim (eps 1e-6), x fp32, y in the precision's type. */
 mf_status mf_op_layernorm(int32_t precision, const float* x, void* y, const float* g, const float* b,
                           int64_t rows, int32_t dim, void* stream);

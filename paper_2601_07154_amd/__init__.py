@@ -259,3 +259,13 @@ def op_quantize_fp8_windows(y, segs, q, srow, stream: int = 0):
     lib = _lib.lib()
     _check(lib.mf_op_quantize_fp8_windows(_ptr(y)[0], y.shape[1], C.c_void_p(s.ctypes.data), s.shape[0], _ptr(q)[0],
                                           _ptr(srow)[0], C.c_void_p(stream)), "mf_op_quantize_fp8_windows")
+
+
+def op_quantize_fp8_windows_noalloc(y, segs, q, srow, stream: int = 0):
+    """As op_quantize_fp8_windows, through the entry point that allocates no device memory (its
+    window table and amax counters sit in the library's static per-GPU array)."""
+    s = np.ascontiguousarray(segs, dtype=np.int32).reshape(-1, 4)
+    lib = _lib.lib()
+    _check(lib.mf_op_quantize_fp8_windows_noalloc(_ptr(y)[0], y.shape[1], C.c_void_p(s.ctypes.data), s.shape[0],
+                                                  _ptr(q)[0], _ptr(srow)[0], C.c_void_p(stream)),
+           "mf_op_quantize_fp8_windows_noalloc")

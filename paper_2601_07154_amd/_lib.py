@@ -107,6 +107,8 @@ EXPORTS = {
     "mf_op_quantize_fp8": (C.c_int32, [C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p]),
     "mf_op_quantize_fp8_windows": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                                C.c_void_p, C.c_void_p]),
+    "mf_op_quantize_fp8_windows_noalloc": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                                       C.c_void_p, C.c_void_p, C.c_void_p]),
     "mf_op_layernorm": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                     C.c_int32, C.c_void_p]),
 }

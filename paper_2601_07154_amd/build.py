@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libmfocus.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["gemm.hip", "attention.hip", "layers.hip", "motion.hip", "exec_hip.cpp", "ops_hip.cpp", "engine.cpp"]
+SOURCES = ["gemm.hip", "attention.hip", "layers.hip", "motion.hip", "exec_hip.cpp", "ops_hip.cpp", "ops_static.hip", "engine.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          # no packed-fp32 VALU instructions in any kernel

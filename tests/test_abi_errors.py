@@ -71,6 +71,16 @@ def test_op_quantize_fp8_windows_rejects(lib, C_, segs):
     from paper_2601_07154_amd import _lib
     arr, p, n = _segs(segs)
     assert lib.mf_op_quantize_fp8_windows(FAKE, C_, p, n, FAKE, FAKE, None) == _lib.MF_EINVAL
+    assert lib.mf_op_quantize_fp8_windows_noalloc(FAKE, C_, p, n, FAKE, FAKE, None) == _lib.MF_EINVAL
+
+
+def test_op_quantize_fp8_windows_noalloc_rejects_more_windows_than_its_array(lib):
+    """The allocation-free quantiser holds at most MF_NOALLOC_MAX_WINDOWS windows (4096)."""
+    from paper_2601_07154_amd import _lib
+    rows = [[8 * i, 1, 8, 8] for i in range(4097)]
+    arr, p, n = _segs(rows)
+    assert lib.mf_op_quantize_fp8_windows_noalloc(FAKE, 32, p, n, FAKE, FAKE, None) == _lib.MF_EINVAL
+    assert lib.mf_op_quantize_fp8_windows_noalloc(FAKE, 32, p, 0, FAKE, FAKE, None) == _lib.MF_EINVAL
 
 
 def test_op_layernorm_rejects_null(lib):
