@@ -45,6 +45,23 @@ mf_status mf_debug_copy(mf_engine* e, int32_t which, void* host, size_t bytes);
 mf_status mf_profile(mf_engine* e, int32_t enable, double* attn_global_ms, int64_t* attn_global_calls,
                      double* attn_frame_ms, double* gemm_ms);
 
+/* Stages of the window forward (Sec. 2.2's per-window inference) timed by the same events. */
+#define MF_STAGE_ATTN_GLOBAL 0  /* attention over every token of a window (odd blocks) */
+#define MF_STAGE_ATTN_FRAME 1   /* attention within each frame (even blocks) */
+#define MF_STAGE_QKV 2          /* LN1 output x W_qkv (head-major Q, K and transposed V) */
+#define MF_STAGE_OUT_PROJ 3     /* attention output x W_o, added to the residual */
+#define MF_STAGE_FC1 4          /* LN2 output x W_1, GELU */
+#define MF_STAGE_FC2 5          /* hidden x W_2, added to the residual */
+#define MF_STAGE_PATCH 6        /* patch-embedding GEMM (with position code and camera tokens) */
+#define MF_STAGE_LAYERNORM 7    /* LN1 and LN2 of every block */
+#define MF_STAGE_QUANT_FP8 8    /* per-window E4M3 activation quantisers (MF_FP8) */
+#define MF_STAGE_HEAD 9         /* final LayerNorm of the camera tokens and the pose head */
+#define MF_STAGE_COUNT 10
+/* Per-stage sums of the timing mf_profile switches on: ms[k] milliseconds and calls[k] launches
+ * of stage k since the last reset, for k < n (n <= MF_STAGE_COUNT is read; arrays host, nullable).
+ * Launches replayed from hipGraphs are included when their batch was captured with timing on. */
+mf_status mf_profile_stages(mf_engine* e, double* ms, int64_t* calls, int32_t n);
+
 /* Attention softmax(Q K^T / sqrt(hd)) V per head within segments.  segs (host): nseg rows of
  * {base, nf, n, npad}: tokens base .. base + nf*npad - 1, frames of n valid tokens every npad
  * rows (keys in padding rows are masked).  Q, K, Vt, O: device, layouts above.

@@ -211,6 +211,15 @@ class Engine:
         return dict(attn_global_ms=ag.value, attn_global_calls=calls.value, attn_frame_ms=af.value,
                     gemm_ms=gm.value)
 
+    def profile_stages(self) -> dict:
+        """Per-stage sums of the current timing: {stage: (ms, launches)} (stage names in _lib.STAGES)."""
+        n = len(_lib.STAGES)
+        ms = np.zeros(n, np.float64)
+        calls = np.zeros(n, np.int64)
+        _check(self.lib.mf_profile_stages(self.h, C.c_void_p(ms.ctypes.data), C.c_void_p(calls.ctypes.data), n),
+               "mf_profile_stages", lib=self.lib)
+        return {name: (float(ms[k]), int(calls[k])) for k, name in enumerate(_lib.STAGES)}
+
 
 def op_attention(precision: str, head_dim: int, heads: int, dim: int, q, k, vt, o, mpad: int, segs,
                  stream: int = 0):

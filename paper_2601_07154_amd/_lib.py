@@ -19,6 +19,7 @@ MF_ANCHOR_YAW, MF_ANCHOR_SE3, MF_ANCHOR_YAW_SCALE = 0, 1, 2
 MF_FOCUS_ACCEL, MF_FOCUS_VELOCITY = 0, 1
 MF_EOS, MF_DEVICE_PTR, MF_POSES_LOCAL = 1, 2, 4
 MF_MAP_MAX, MF_MAP_SUM = 0, 1
+STAGES = ("attn_global", "attn_frame", "qkv", "out_proj", "fc1", "fc2", "patch", "layernorm", "quant_fp8", "head")
 
 
 class ModelCfg(C.Structure):
@@ -98,6 +99,7 @@ EXPORTS = {
     "mf_debug_copy": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "mf_profile": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "mf_profile_stages": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "mf_op_attention": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
     "mf_op_gemm": (C.c_int32, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,

@@ -840,4 +840,11 @@ mf_status mf_profile(mf_engine* e, int32_t enable, double* ag, int64_t* calls, d
   return MF_OK;
 }
 
+mf_status mf_profile_stages(mf_engine* e, double* ms, int64_t* calls, int32_t n) {
+  if (!e || n < 0) return MF_EINVAL;
+  std::lock_guard<std::mutex> lk(e->mu);
+  e->ex->profile_stages(ms, calls, n < MF_STAGE_COUNT ? n : MF_STAGE_COUNT);
+  return MF_OK;
+}
+
 }  // extern "C"

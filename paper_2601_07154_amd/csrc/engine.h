@@ -70,6 +70,13 @@ class Executor {
   virtual mf_status debug_copy(int which, void* host, size_t bytes, std::string& err) = 0;
   virtual void profile(double* attn_global_ms, int64_t* attn_global_calls, double* attn_frame_ms,
                        double* gemm_ms, int enable) = 0;
+  // per-stage sums (MF_STAGE_* order) of the same timing; executors without it report zeros
+  virtual void profile_stages(double* ms, int64_t* calls, int n) {
+    for (int k = 0; k < n; ++k) {
+      if (ms) ms[k] = 0.0;
+      if (calls) calls[k] = 0;
+    }
+  }
 };
 
 Executor* make_executor();   // provided by the linked executor (HIP, or the CPU test stub)

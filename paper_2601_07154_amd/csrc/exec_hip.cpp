@@ -14,6 +14,7 @@
 
 #include "engine.h"
 #include "kernels.h"
+#include "../../include/mf_ops.h"
 
 namespace mf {
 
@@ -406,14 +407,24 @@ class HipExecutor : public Executor {
     // may run on an API thread while the scheduler thread runs a batch: the switch and the sums are
     // shared under prof_mu_, and a batch reads the switch once, when it starts (latch_profiling)
     std::lock_guard<std::mutex> lk(prof_mu_);
-    if (ag_ms) *ag_ms = prof_ag_ms_;
-    if (ag_calls) *ag_calls = prof_ag_calls_;
-    if (af_ms) *af_ms = prof_af_ms_;
-    if (g_ms) *g_ms = prof_gemm_ms_;
+    if (ag_ms) *ag_ms = prof_ms_[MF_STAGE_ATTN_GLOBAL];
+    if (ag_calls) *ag_calls = prof_calls_[MF_STAGE_ATTN_GLOBAL];
+    if (af_ms) *af_ms = prof_ms_[MF_STAGE_ATTN_FRAME];
+    if (g_ms) {
+      *g_ms = 0.0;
+      for (int k : {MF_STAGE_QKV, MF_STAGE_OUT_PROJ, MF_STAGE_FC1, MF_STAGE_FC2, MF_STAGE_PATCH}) *g_ms += prof_ms_[k];
+    }
     if (enable >= 0) {
       profiling_ = enable != 0;
-      prof_ag_ms_ = prof_af_ms_ = prof_gemm_ms_ = 0.0;
-      prof_ag_calls_ = 0;
+      for (int k = 0; k < MF_STAGE_COUNT; ++k) { prof_ms_[k] = 0.0; prof_calls_[k] = 0; }
+    }
+  }
+
+  void profile_stages(double* ms, int64_t* calls, int n) override {
+    std::lock_guard<std::mutex> lk(prof_mu_);
+    for (int k = 0; k < n && k < MF_STAGE_COUNT; ++k) {
+      if (ms) ms[k] = prof_ms_[k];
+      if (calls) calls[k] = prof_calls_[k];
     }
   }
 
@@ -622,15 +633,24 @@ class HipExecutor : public Executor {
     g.A = Hb_; g.lda = KP; g.Bt = Wp_; g.ldb = KP; g.M = M; g.N = D; g.K = KP;
     g.bias = b_p_; g.C = X_; g.ldc = D; g.N = D;
     g.rowinfo = rowinfo_; g.pe = pe_; g.c_ref = c_ref_; g.c_other = c_other_;
-    HIPCHECK(run_gemm(EPI_PATCH, g));
+    HIPCHECK(run_gemm(EPI_PATCH, g, MF_STAGE_PATCH));
     // fp8: activations feeding the QKV and MLP GEMMs are quantised per window (dynamic scales)
     const int nwin = (int)p.gsegs.size();
     auto quant = [&](const void* y, int C, unsigned char* q, float* srow) {
-      return window_quant_fp8((const __bf16*)y, C, gsegs, nwin, p.max_rows, amax_, q, srow, st_);
+      prof_begin();
+      const hipError_t r = window_quant_fp8((const __bf16*)y, C, gsegs, nwin, p.max_rows, amax_, q, srow, st_);
+      prof_end(MF_STAGE_QUANT_FP8);
+      return r;
+    };
+    auto ln = [&](const float* g_, const float* b_) {
+      prof_begin();
+      const hipError_t r = layernorm(dt_, X_, Y_, g_, b_, M, D, nullptr, st_);
+      prof_end(MF_STAGE_LAYERNORM);
+      return r;
     };
     for (int l = 0; l < layers; ++l) {
       const LayerW& L = layers_[l];
-      HIPCHECK(layernorm(dt_, X_, Y_, L.ln1_g, L.ln1_b, M, D, nullptr, st_));
+      HIPCHECK(ln(L.ln1_g, L.ln1_b));
       GemmArgs q{};
       q.A = Y_; q.lda = D; q.Bt = L.Wqkv; q.ldb = D; q.M = M; q.N = 3 * D; q.K = D; q.bias = L.b_qkv;
       q.q = Q_; q.k = K_; q.vt = Vt_; q.heads = H_; q.hd = hd_; q.mpad = mpad_;
@@ -641,18 +661,18 @@ class HipExecutor : public Executor {
         q.ascale = srow_;
         q.bscale = wscale_ + 3 * l;
       }
-      HIPCHECK(run_gemm(EPI_QKV, q, fp8_));
+      HIPCHECK(run_gemm(EPI_QKV, q, MF_STAGE_QKV, fp8_));
       const bool global = (l % 2) == 1;
       prof_begin();
       if (global)
         HIPCHECK(attention(dt_, hd_, Q_, K_, Vt_, O_, mpad_, H_, D, gsegs, gwork, (int)p.gwork.size(), st_));
       else
         HIPCHECK(attention(dt_, hd_, Q_, K_, Vt_, O_, mpad_, H_, D, fsegs, fwork, (int)p.fwork.size(), st_));
-      prof_end(global ? 1 : 2);
+      prof_end(global ? MF_STAGE_ATTN_GLOBAL : MF_STAGE_ATTN_FRAME);
       GemmArgs o{};
       o.A = O_; o.lda = D; o.Bt = L.Wo; o.ldb = D; o.M = M; o.N = D; o.K = D; o.bias = L.b_o; o.C = X_; o.ldc = D;
-      HIPCHECK(run_gemm(EPI_RESID, o));
-      HIPCHECK(layernorm(dt_, X_, Y_, L.ln2_g, L.ln2_b, M, D, nullptr, st_));
+      HIPCHECK(run_gemm(EPI_RESID, o, MF_STAGE_OUT_PROJ));
+      HIPCHECK(ln(L.ln2_g, L.ln2_b));
       GemmArgs f1{};
       f1.A = Y_; f1.lda = D; f1.Bt = L.W1; f1.ldb = D; f1.M = M; f1.N = F_; f1.K = D; f1.bias = L.b_1;
       f1.C = Hb_; f1.ldc = F_;
@@ -662,7 +682,7 @@ class HipExecutor : public Executor {
         f1.ascale = srow_;
         f1.bscale = wscale_ + 3 * l + 1;
       }
-      HIPCHECK(run_gemm(EPI_GELU, f1, fp8_));
+      HIPCHECK(run_gemm(EPI_GELU, f1, MF_STAGE_FC1, fp8_));
       GemmArgs f2{};
       f2.A = Hb_; f2.lda = F_; f2.Bt = L.W2; f2.ldb = F_; f2.M = M; f2.N = D; f2.K = F_; f2.bias = L.b_2;
       f2.C = X_; f2.ldc = D;
@@ -672,24 +692,26 @@ class HipExecutor : public Executor {
         f2.ascale = srow2_;
         f2.bscale = wscale_ + 3 * l + 2;
       }
-      HIPCHECK(run_gemm(EPI_RESID, f2, fp8_));
+      HIPCHECK(run_gemm(EPI_RESID, f2, MF_STAGE_FC2, fp8_));
     }
     if (layers == depth_) {
       const int Fr = (int)p.frames.size();
+      prof_begin();
       HIPCHECK(layernorm(DT_F32, X_, camln_, lnf_g_, lnf_b_, Fr, D, cam_rows, st_));
       GemmArgs h{};
       h.A = camln_; h.lda = D; h.Bt = H1t_; h.ldb = D; h.M = Fr; h.N = D; h.K = D; h.bias = h_1_;
       h.C = camg_; h.ldc = D;
       HIPCHECK(gemm(DT_F32, EPI_GELU, h, st_));
       HIPCHECK(pose_out(camg_, H_2_, h_2_, Fr, D, pose9_, tloc_, st_));
+      prof_end(MF_STAGE_HEAD);
     }
     return MF_OK;
   }
 
-  hipError_t run_gemm(Epi e, const GemmArgs& a, bool fp8 = false) {
+  hipError_t run_gemm(Epi e, const GemmArgs& a, int stage, bool fp8 = false) {
     prof_begin();
     const hipError_t r = gemm(fp8 ? DT_FP8 : dt_, e, a, st_);
-    prof_end(3);
+    prof_end(stage);
     return r;
   }
 
@@ -707,7 +729,7 @@ class HipExecutor : public Executor {
       ProfEv e;
       hipEventCreate(&e.a);
       hipEventCreate(&e.b);
-      e.kind = 0;
+      e.kind = -1;
       prof_target_->push_back(e);
       hipEventRecord(e.a, st_);
       return;
@@ -735,9 +757,10 @@ class HipExecutor : public Executor {
     float ms = 0.0f;
     hipEventSynchronize(e.b);
     hipEventElapsedTime(&ms, e.a, e.b);
-    if (e.kind == 1) { prof_ag_ms_ += ms; prof_ag_calls_++; }
-    else if (e.kind == 2) prof_af_ms_ += ms;
-    else prof_gemm_ms_ += ms;
+    if (e.kind >= 0 && e.kind < MF_STAGE_COUNT) {
+      prof_ms_[e.kind] += ms;
+      prof_calls_[e.kind]++;
+    }
   }
   void collect_profile(std::string&) {
     std::lock_guard<std::mutex> lk(prof_mu_);
@@ -836,8 +859,8 @@ class HipExecutor : public Executor {
   std::map<std::string, GraphEntry> graphs_;
   std::vector<ProfEv>* prof_target_ = nullptr;
   const std::vector<ProfEv>* replayed_prof_ = nullptr;
-  double prof_ag_ms_ = 0, prof_af_ms_ = 0, prof_gemm_ms_ = 0;
-  int64_t prof_ag_calls_ = 0;
+  double prof_ms_[MF_STAGE_COUNT] = {};     // summed event times per MF_STAGE_* since the last reset
+  int64_t prof_calls_[MF_STAGE_COUNT] = {};
 };
 
 Executor* make_executor() { return new HipExecutor(); }
