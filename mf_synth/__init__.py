@@ -11,6 +11,8 @@ that y = x W + b):
     per layer l:  ln1.g[D], ln1.b[D], W_qkv[D, 3D], b_qkv[3D], W_o[D, D], b_o[D],
                   ln2.g[D], ln2.b[D], W_1[D, F], b_1[F], W_2[F, D], b_2[D]
     lnf.g[D], lnf.b[D], H_1[D, D], h_1[D], H_2[D, 9], h_2[9]
+    with a depth head (ModelConfig.depth_head), appended:
+    lnd.g[D], lnd.b[D], W_d[D, 196], b_d[196]
 Every entry is N(0, 0.02) drawn in float64 and rounded to fp32; LayerNorm
 gains are 1 + N(0, 0.02).  W_qkv columns are q | k | v, each split into heads
 of hd contiguous columns.
@@ -33,6 +35,7 @@ class ModelConfig:
     heads: int
     mlp: int
     patch: int = PATCH
+    depth_head: bool = False      # the blob also carries the per-patch depth head
 
     @property
     def head_dim(self) -> int:
@@ -89,6 +92,9 @@ def weight_spec(cfg: ModelConfig):
                  (p + "W_2", (F, D)), (p + "b_2", (D,))]
     spec += [("lnf.g", (D,)), ("lnf.b", (D,)), ("H_1", (D, D)), ("h_1", (D,)),
              ("H_2", (D, POSE_DIM)), ("h_2", (POSE_DIM,))]
+    if cfg.depth_head:
+        P2 = cfg.patch * cfg.patch
+        spec += [("lnd.g", (D,)), ("lnd.b", (D,)), ("W_d", (D, P2)), ("b_d", (P2,))]
     return spec
 
 

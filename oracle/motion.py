@@ -126,7 +126,7 @@ def scale_translation(Tl: np.ndarray, rho: float) -> np.ndarray:
     return out
 
 
-def chain_windows(schedule, local_poses, mode: int = ANCHOR_YAW) -> np.ndarray:
+def chain_windows(schedule, local_poses, mode: int = ANCHOR_YAW, return_scales: bool = False):
     """Stitch per-window local poses into world poses of every emitted frame.
 
     schedule: output of window_schedule; local_poses[k]: [size_k, 4, 4] world(window-local)
@@ -134,11 +134,15 @@ def chain_windows(schedule, local_poses, mode: int = ANCHOR_YAW) -> np.ndarray:
     ANCHOR_YAW_SCALE first rescales window k's translations by window_scale (monocular windows
     carry independent scale; the paper's rigid chaining keeps each window's), then anchors as
     ANCHOR_YAW.
+    return_scales: also return each window's scale factor (1 except in ANCHOR_YAW_SCALE), by which
+    the window's depth maps are multiplied to live in the world's units.
     """
     n = schedule[-1]["emit_end"] if schedule else 0
     T_w = np.zeros((n, 4, 4))
+    scales = []
     for k, win in enumerate(schedule):
         Tl = local_poses[k]
+        rho = 1.0
         if k == 0:
             A = np.eye(4)
         else:
@@ -146,11 +150,13 @@ def chain_windows(schedule, local_poses, mode: int = ANCHOR_YAW) -> np.ndarray:
             if a < win["start"]:
                 raise ValueError("consecutive windows share no frame (overlap 0)")
             if mode == ANCHOR_YAW_SCALE:
-                Tl = scale_translation(Tl, window_scale(win, Tl, T_w))
+                rho = window_scale(win, Tl, T_w)
+                Tl = scale_translation(Tl, rho)
             A = alignment(Tl[a - win["start"]], T_w[a], ANCHOR_YAW if mode == ANCHOR_YAW_SCALE else mode)
+        scales.append(rho)
         for t in range(win["emit_begin"], win["emit_end"]):
             T_w[t] = Tl[t - win["start"]] @ A
-    return T_w
+    return (T_w, scales) if return_scales else T_w
 
 
 # ----------------------------------------------------------------------------- focus

@@ -10,6 +10,13 @@ global attention over every token of the window (odd layers), an erf-GELU MLP,
 and a camera-token head regressing 9 numbers (translation 3, quaternion 4
 scalar-last, field of view 2) per frame.
 
+The window forward of Sec. 2.2 predicts depth maps {D_t} beside the poses; the
+paper does not describe that head either.  The optional one computed here
+(depth_head) is the simplest dense head on the same tokens: a LayerNorm with its
+own affine on every patch token of the last block, a linear map to the 14 x 14
+pixels of that patch (row-major within the patch), and exp of the result, so a
+depth map is positive and in the window's own (local) units.
+
 Options
   precision="fp64"  plain float64 everywhere (the parity reference)
   precision="bf16"  every matmul operand (and the softmax probabilities before
@@ -92,8 +99,10 @@ class Prec:
 
 
 # ----------------------------------------------------------------------------- weights
-def unpack_weights(blob: np.ndarray, depth: int, dim: int, mlp: int, patch: int = 14) -> dict:
-    """Split the flat fp32 blob into named float64 tensors (order of the blob format)."""
+def unpack_weights(blob: np.ndarray, depth: int, dim: int, mlp: int, patch: int = 14,
+                   depth_head: bool = False) -> dict:
+    """Split the flat fp32 blob into named float64 tensors (order of the blob format; with
+    depth_head the depth head's lnd_g, lnd_b, W_d [D, patch^2], b_d follow the pose head)."""
     blob = np.asarray(blob, dtype=np.float32).astype(np.float64)
     pos = 0
 
@@ -120,6 +129,11 @@ def unpack_weights(blob: np.ndarray, depth: int, dim: int, mlp: int, patch: int 
     w["h_1"] = take(D)
     w["H_2"] = take(D, 9)
     w["h_2"] = take(9)
+    if depth_head:
+        w["lnd_g"] = take(D)
+        w["lnd_b"] = take(D)
+        w["W_d"] = take(D, patch * patch)
+        w["b_d"] = take(patch * patch)
     if pos != blob.size:
         raise ValueError(f"weight blob has {blob.size - pos} trailing values")
     return w
@@ -256,6 +270,22 @@ def pose_head(cam_tokens: np.ndarray, w: dict) -> np.ndarray:
     return gelu(z @ w["H_1"] + w["h_1"]) @ w["H_2"] + w["h_2"]
 
 
+def depth_head(tokens: np.ndarray, w: dict, S: int, height: int, width: int, patch: int = 14,
+               prec: Prec | None = None) -> np.ndarray:
+    """Depth maps [S, H, W] of a window from its last-block tokens [S*n, D]: every patch token
+    (not the camera token) goes through LN(lnd) and W_d, b_d to patch*patch values, exp'd, that
+    fill the patch's pixels row by row: pixel (py*patch + ky, px*patch + kx) of frame f takes
+    output ky*patch + kx of patch (py, px)."""
+    prec = prec or Prec()
+    gh, gw = height // patch, width // patch
+    n = gh * gw + 1
+    D = tokens.shape[1]
+    x = tokens.reshape(S, n, D)[:, 1:, :]
+    z = prec.matmul(layer_norm(x, w["lnd_g"], w["lnd_b"]), w["W_d"]) + w["b_d"]   # [S, P, patch^2]
+    d = np.exp(z).reshape(S, gh, gw, patch, patch)
+    return d.transpose(0, 1, 3, 2, 4).reshape(S, gh * patch, gw * patch)
+
+
 def pose9_to_T(p9: np.ndarray) -> np.ndarray:
     """World-to-camera 4x4 [R(q) | t] from one 9-vector."""
     T = np.eye(4)
@@ -265,11 +295,13 @@ def pose9_to_T(p9: np.ndarray) -> np.ndarray:
 
 
 def forward_window(frames: np.ndarray, w: dict, heads: int, patch: int = 14,
-                   precision: str = "fp64", return_tokens: bool = False, workers: int = 1):
+                   precision: str = "fp64", return_tokens: bool = False, workers: int = 1,
+                   depth: bool = False):
     """Pose regression for one window of S frames [S,3,H,W] -> pose9 [S, 9].
 
     Even layers attend within each frame (n = P+1 tokens), odd layers over all S*n tokens.
     workers: threads over the attention heads (same values for any count).
+    depth: also return the window's depth maps [S, H, W] (depth_head): (p9, depth[, tokens]).
     """
     prec = Prec(precision)
     S, _, H, W = frames.shape
@@ -280,4 +312,9 @@ def forward_window(frames: np.ndarray, w: dict, heads: int, patch: int = 14,
     for l, lw in enumerate(w["layers"]):
         x = block(x, lw, heads, frame_groups if l % 2 == 0 else window_group, prec, workers)
     p9 = pose_head(x[0::n], w)
-    return (p9, x) if return_tokens else p9
+    out = (p9,)
+    if depth:
+        out += (depth_head(x, w, S, H, W, patch, prec),)
+    if return_tokens:
+        out += (x,)
+    return out if len(out) > 1 else p9
