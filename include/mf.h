@@ -75,6 +75,8 @@ typedef struct mf_model_cfg {
   int32_t mlp;        /* MLP hidden width (multiple of 128) */
   int32_t patch;      /* must be 14 */
   int32_t precision;  /* MF_FP32, MF_BF16 or MF_FP8 */
+  int32_t depth_head; /* 1: the blob also carries the depth head (below), so streams may emit the
+                         depth maps {D_t} that Sec. 2.2's window forward predicts beside the poses */
 } mf_model_cfg;
 
 typedef struct mf_runtime_cfg {
@@ -110,6 +112,7 @@ typedef struct mf_stream_cfg {
   int32_t focus_mode;           /* MF_FOCUS_ACCEL (Eq. 3, the paper's) or MF_FOCUS_VELOCITY (Eq. 2) */
   int32_t diff_stride;          /* frames between the differenced centres, 1..64 (0: 1, the paper's) */
   int32_t map_mode;             /* MF_MAP_MAX or MF_MAP_SUM: the map normaliser Z of Eq. 7 */
+  int32_t emit_depth;           /* 1: keep every emitted frame's depth map (model with depth_head) */
 } mf_stream_cfg;
 
 /* One emitted frame.  valid bit 0: focus point defined (t >= 2 s, or t >= s for velocity;
@@ -149,6 +152,8 @@ typedef struct mf_stats {
  * allocates the per-batch workspace, creates the stream and (threaded) the scheduler.
  * Blob order: W_p[588,D] b_p c_ref c_other, per layer {ln1.g ln1.b W_qkv[D,3D] b_qkv W_o b_o
  * ln2.g ln2.b W_1[D,F] b_1 W_2[F,D] b_2}, lnf.g lnf.b H_1[D,D] h_1 H_2[D,9] h_2;
+ * with depth_head, then lnd.g lnd.b W_d[D,196] b_d[196]: the depth of pixel (14 py + ky, 14 px + kx)
+ * is exp of output ky*14 + kx of LN_d(patch token (py, px)) W_d + b_d, in the window's units;
  * linear layers stored [in, out].  n_floats must match exactly (MF_EINVAL otherwise). */
 mf_status mf_engine_create(const mf_model_cfg* model, const float* weights, size_t n_floats,
                            const mf_runtime_cfg* rt, mf_engine** out);
@@ -184,6 +189,15 @@ mf_status mf_push_poses(mf_engine* e, int32_t stream_id, const double* T_w2c, in
  * MF_EAGAIN: nothing ready now; MF_ECLOSED: closed and fully drained (the id is released). */
 mf_status mf_poll_focus(mf_engine* e, int32_t stream_id, mf_focus* out, int32_t cap,
                         int32_t* n_out, float* maps, int32_t maps_flags);
+
+/* Sec. 2.2 (the window forward predicts depth maps {D_t} beside the poses; only frames not emitted
+ * before are emitted): mf_poll_focus, plus each returned frame's depth map into depth (nullable;
+ * [cap][H][W] fp32, host, or device memory with MF_DEVICE_PTR in flags, which also applies to maps).
+ * A frame's depth is that of the window that emits it, camera-relative, multiplied by the window's
+ * anchoring scale under MF_ANCHOR_YAW_SCALE (1 otherwise).  MF_EINVAL if depth is given for a
+ * stream opened without emit_depth. */
+mf_status mf_poll_focus_depth(mf_engine* e, int32_t stream_id, mf_focus* out, int32_t cap, int32_t* n_out,
+                              float* maps, float* depth, int32_t flags);
 
 /* End of stream (Sec. 2.2's windows, with this library's tail window [N - L, N) for frames the
  * regular windows left out): no more pushes; the tail window is scheduled; results stay pollable. */

@@ -79,11 +79,12 @@ class Engine:
     def __init__(self, depth: int, dim: int, heads: int, mlp: int, weights: np.ndarray,
                  precision: str = "bf16", threaded: bool = False, max_tokens: int = 0,
                  hbm_budget: int = 0, device: int = 0, stream: int | None = None, graphs: bool = True,
-                 allocator: str | None = None, lib=None):
-        """allocator="torch": the engine's device memory comes from torch's caching allocator."""
+                 allocator: str | None = None, depth_head: bool = False, lib=None):
+        """allocator="torch": the engine's device memory comes from torch's caching allocator.
+        depth_head: the weight blob also carries the depth head (streams may emit depth maps)."""
         self.lib = lib or _lib.lib()
         w = np.ascontiguousarray(weights, dtype=np.float32)
-        m = _lib.ModelCfg(depth, dim, heads, mlp, 14, PRECISIONS[precision])
+        m = _lib.ModelCfg(depth, dim, heads, mlp, 14, PRECISIONS[precision], 1 if depth_head else 0)
         rt = _lib.RuntimeCfg(device, 1 if threaded else 0, max_tokens, hbm_budget,
                              C.c_void_p(stream) if stream else None, 1 if graphs else 0, 0)
         self._alloc = None
@@ -102,7 +103,8 @@ class Engine:
 
     @classmethod
     def from_model(cls, model, weights, **kw):
-        return cls(model.depth, model.dim, model.heads, model.mlp, weights, **kw)
+        return cls(model.depth, model.dim, model.heads, model.mlp, weights,
+                   depth_head=getattr(model, "depth_head", False), **kw)
 
     def close(self):
         if getattr(self, "h", None):
@@ -126,11 +128,11 @@ class Engine:
                     sigma: float = 1.0, sigma_min: float = 0.0, sigma_max: float = 0.0,
                     anchor_mode: int = MF_ANCHOR_YAW, emit_maps: bool = True, ring_frames: int = 0,
                     result_frames: int = 0, allow_again: bool = False, focus_mode: int = 0,
-                    diff_stride: int = 1, map_mode: int = MF_MAP_MAX) -> int:
+                    diff_stride: int = 1, map_mode: int = MF_MAP_MAX, emit_depth: bool = False) -> int:
         fx, fy, cx, cy = K
         c = _lib.StreamCfg(height, width, window, overlap, fx, fy, cx, cy, n_points, anchor_mode, sigma,
                            sigma_min, sigma_max, 1 if emit_maps else 0, ring_frames, result_frames, focus_mode,
-                           diff_stride, map_mode)
+                           diff_stride, map_mode, 1 if emit_depth else 0)
         sid = C.c_int32()
         st = self.lib.mf_open_stream(self.h, C.byref(c), C.byref(sid))
         if allow_again and st == MF_EAGAIN:
@@ -159,14 +161,23 @@ class Engine:
     def close_stream(self, sid: int):
         _check(self.lib.mf_close_stream(self.h, sid), "mf_close_stream", lib=self.lib)
 
-    def poll(self, sid: int, cap: int = 4096, maps=None):
-        """Returns (records [n] FOCUS_DTYPE, status) with status MF_OK, MF_EAGAIN or MF_ECLOSED."""
+    def poll(self, sid: int, cap: int = 4096, maps=None, depth=None):
+        """Returns (records [n] FOCUS_DTYPE, status) with status MF_OK, MF_EAGAIN or MF_ECLOSED.
+        maps / depth (optional): [cap][H][W] float32, both host or both device."""
         out = np.zeros(cap, dtype=FOCUS_DTYPE)
         n = C.c_int32()
         mp, mdev = (None, False) if maps is None else _ptr(maps)
-        st = self.lib.mf_poll_focus(self.h, sid, C.c_void_p(out.ctypes.data), cap, C.byref(n), mp,
-                                    MF_DEVICE_PTR if mdev else 0)
-        _check(st, "mf_poll_focus", (MF_OK, MF_EAGAIN, MF_ECLOSED), lib=self.lib)
+        if depth is None:
+            st = self.lib.mf_poll_focus(self.h, sid, C.c_void_p(out.ctypes.data), cap, C.byref(n), mp,
+                                        MF_DEVICE_PTR if mdev else 0)
+            _check(st, "mf_poll_focus", (MF_OK, MF_EAGAIN, MF_ECLOSED), lib=self.lib)
+        else:
+            dp, ddev = _ptr(depth)
+            if maps is not None and mdev != ddev:
+                raise ValueError("maps and depth must both be host or both device memory")
+            st = self.lib.mf_poll_focus_depth(self.h, sid, C.c_void_p(out.ctypes.data), cap, C.byref(n), mp, dp,
+                                              MF_DEVICE_PTR if ddev else 0)
+            _check(st, "mf_poll_focus_depth", (MF_OK, MF_EAGAIN, MF_ECLOSED), lib=self.lib)
         return out[:n.value].copy(), st
 
     def step(self) -> int:

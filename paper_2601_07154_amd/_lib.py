@@ -24,7 +24,7 @@ STAGES = ("attn_global", "attn_frame", "qkv", "out_proj", "fc1", "fc2", "patch",
 
 class ModelCfg(C.Structure):
     _fields_ = [("depth", C.c_int32), ("dim", C.c_int32), ("heads", C.c_int32), ("mlp", C.c_int32),
-                ("patch", C.c_int32), ("precision", C.c_int32)]
+                ("patch", C.c_int32), ("precision", C.c_int32), ("depth_head", C.c_int32)]
 
 
 DEV_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -44,7 +44,8 @@ class StreamCfg(C.Structure):
                 ("n_points", C.c_int32), ("anchor_mode", C.c_int32),
                 ("sigma", C.c_double), ("sigma_min", C.c_double), ("sigma_max", C.c_double),
                 ("emit_maps", C.c_int32), ("ring_frames", C.c_int32), ("result_frames", C.c_int32),
-                ("focus_mode", C.c_int32), ("diff_stride", C.c_int32), ("map_mode", C.c_int32)]
+                ("focus_mode", C.c_int32), ("diff_stride", C.c_int32), ("map_mode", C.c_int32),
+                ("emit_depth", C.c_int32)]
 
 
 class Focus(C.Structure):
@@ -86,6 +87,8 @@ EXPORTS = {
     "mf_push_poses": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int64, C.c_int32]),
     "mf_poll_focus": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
                                   C.c_void_p, C.c_int32]),
+    "mf_poll_focus_depth": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                        C.c_void_p, C.c_void_p, C.c_int32]),
     "mf_close_stream": (C.c_int32, [C.c_void_p, C.c_int32]),
     "mf_engine_step": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
     "mf_engine_sync": (C.c_int32, [C.c_void_p]),

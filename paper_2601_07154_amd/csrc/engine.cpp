@@ -91,6 +91,8 @@ struct Engine {
 // Frames of history the device looks back on beyond those a batch emits: the N map points, the
 // anchor inside the window, and the 2 s frames of the centre differences.
 static int hist_lookback(const mf_stream_cfg& c) { return c.n_points + c.window + 8 + 2 * c.diff_stride; }
+// streams that keep per-frame maps (focus maps, depth maps) in result slots until they are polled
+static bool keeps_results(const mf_stream_cfg& c) { return c.emit_maps || c.emit_depth; }
 
 // ------------------------------------------------------------------ schedule
 // The next window of a frame stream if all its frames are here (not committed).
@@ -138,7 +140,7 @@ static void commit_window(Stream& s, const BatchWindow& w) {
 }
 
 static bool maps_fit(const Stream& s, int64_t emit_end) {
-  return !s.cfg.emit_maps || emit_end - s.polled <= s.res.map_cap;
+  return !keeps_results(s.cfg) || emit_end - s.polled <= s.res.map_cap;
 }
 
 static bool work_ready_locked(Engine& e) {
@@ -427,6 +429,10 @@ mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream
     set_err("unknown map mode %d", c.map_mode);
     return MF_EINVAL;
   }
+  if (c.emit_depth && !e->model.depth_head) {
+    set_err("emit_depth needs a model with a depth head");
+    return MF_EINVAL;
+  }
   if (c.diff_stride == 0) c.diff_stride = 1;
   if (c.diff_stride < 1 || c.diff_stride > 64) {
     set_err("diff_stride must be in 1..64");
@@ -462,7 +468,7 @@ mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream
   // plus what the maps, the anchor and the differences look back on
   int hist_n = 64;
   while (hist_n < std::max(8 * c.window, 256) + hist_lookback(c)) hist_n *= 2;
-  const uint64_t need = e->ex->stream_bytes(c, c.ring_frames, c.emit_maps ? c.result_frames : 0, hist_n);
+  const uint64_t need = e->ex->stream_bytes(c, c.ring_frames, keeps_results(c) ? c.result_frames : 0, hist_n);
   auto s = std::make_shared<Stream>();
   {
     std::lock_guard<std::mutex> lk(e->mu);
@@ -486,7 +492,7 @@ mf_status mf_open_stream(mf_engine* e, const mf_stream_cfg* cfg, int32_t* stream
   }
   s->cfg = c;
   s->res.ring_cap = c.ring_frames;
-  s->res.map_cap = c.emit_maps ? c.result_frames : 0;
+  s->res.map_cap = keeps_results(c) ? c.result_frames : 0;
   s->res.hist_n = hist_n;
   std::string err;
   const mf_status rc = e->ex->open_stream(c, &s->res, err);
@@ -586,6 +592,10 @@ mf_status mf_push_poses(mf_engine* e, int32_t stream_id, const double* T, int32_
     set_err("stream %d takes frames, not poses", stream_id);
     return MF_EINVAL;
   }
+  if (s->cfg.emit_depth) {
+    set_err("stream %d emits depth maps: depth comes from frames, not poses", stream_id);
+    return MF_EINVAL;
+  }
   if (n > e->ex->max_frames()) {
     set_err("at most %lld poses per call", (long long)e->ex->max_frames());
     return MF_EINVAL;
@@ -630,7 +640,7 @@ mf_status mf_push_poses(mf_engine* e, int32_t stream_id, const double* T, int32_
       j.emit_begin = first_frame;
       j.emit_end = first_frame + n;
     }
-    if (s->cfg.emit_maps && j.emit_end - j.emit_begin > s->res.map_cap) {
+    if (keeps_results(s->cfg) && j.emit_end - j.emit_begin > s->res.map_cap) {
       set_err("%lld frames at once exceed result_frames %d", (long long)(j.emit_end - j.emit_begin),
               s->res.map_cap);
       return MF_EINVAL;
@@ -657,6 +667,11 @@ mf_status mf_push_poses(mf_engine* e, int32_t stream_id, const double* T, int32_
 
 mf_status mf_poll_focus(mf_engine* e, int32_t stream_id, mf_focus* out, int32_t cap, int32_t* n_out,
                         float* maps, int32_t maps_flags) {
+  return mf_poll_focus_depth(e, stream_id, out, cap, n_out, maps, nullptr, maps_flags);
+}
+
+mf_status mf_poll_focus_depth(mf_engine* e, int32_t stream_id, mf_focus* out, int32_t cap, int32_t* n_out,
+                              float* maps, float* depth, int32_t maps_flags) {
   GUARD_BEGIN
   if (!e || !n_out || cap < 0 || (cap > 0 && !out)) {
     set_err("bad arguments");
@@ -671,6 +686,10 @@ mf_status mf_poll_focus(mf_engine* e, int32_t stream_id, mf_focus* out, int32_t 
   if (!s) {
     set_err("unknown stream %d", stream_id);
     return MF_ENOTFOUND;
+  }
+  if (depth && !s->cfg.emit_depth) {
+    set_err("stream %d was opened without emit_depth", stream_id);
+    return MF_EINVAL;
   }
   std::lock_guard<std::mutex> io(s->io);
   int32_t k = 0;
@@ -702,7 +721,9 @@ mf_status mf_poll_focus(mf_engine* e, int32_t stream_id, mf_focus* out, int32_t 
     }
   }
   // copy the maps before releasing their ring slots (the scheduler may reuse them afterwards)
-  if (maps && s->cfg.emit_maps) {
+  for (int kind = 0; kind < 2; ++kind) {
+    float* dst = kind == 0 ? (s->cfg.emit_maps ? maps : nullptr) : (s->cfg.emit_depth ? depth : nullptr);
+    if (!dst) continue;
     const int64_t hw = (int64_t)s->cfg.height * s->cfg.width;
     int32_t i = 0;
     while (i < k) {
@@ -710,8 +731,9 @@ mf_status mf_poll_focus(mf_engine* e, int32_t stream_id, mf_focus* out, int32_t 
       int32_t run = 1;
       while (i + run < k && out[i + run].frame == f0 + run && (f0 + run) % s->res.map_cap != 0) ++run;
       std::string err;
-      const mf_status rc = e->ex->copy_maps(s->cfg, &s->res, f0, run, maps + (int64_t)i * hw,
-                                            (maps_flags & MF_DEVICE_PTR) != 0, err);
+      const bool dev = (maps_flags & MF_DEVICE_PTR) != 0;
+      const mf_status rc = kind == 0 ? e->ex->copy_maps(s->cfg, &s->res, f0, run, dst + (int64_t)i * hw, dev, err)
+                                     : e->ex->copy_depth(s->cfg, &s->res, f0, run, dst + (int64_t)i * hw, dev, err);
       if (rc != MF_OK) {
         set_err("%s", err.c_str());
         return rc;

@@ -13,7 +13,8 @@ namespace mf {
 // Device resources of one stream, owned by the executor.
 struct StreamRes {
   void* ring = nullptr;      // frame ring [ring_cap][3][H][W] fp32
-  void* maps = nullptr;      // map ring [map_cap][H][W] fp32
+  void* maps = nullptr;      // map ring [map_cap][H][W] fp32 (emit_maps)
+  void* depth = nullptr;     // depth-map ring [map_cap][H][W] fp32 (emit_depth)
   void* hist = nullptr;      // FP64 pose/acceleration history [hist_n]
   int ring_cap = 0, map_cap = 0, hist_n = 0;
   int pe_base = 0;           // first row of this resolution in the position-code table
@@ -51,6 +52,8 @@ class Executor {
   virtual int64_t max_tokens() const = 0;
   virtual int64_t max_frames() const = 0;     // frames (pose rows and emitted records) per batch
   virtual int rows_per_frame(int H, int W) const = 0;   // token rows a frame occupies
+  // device bytes of a stream: frame ring, map_cap result slots of each kept map kind (focus maps if
+  // c.emit_maps, depth maps if c.emit_depth) and the history
   virtual uint64_t stream_bytes(const mf_stream_cfg& c, int ring_cap, int map_cap, int hist_n) const = 0;
   virtual mf_status open_stream(const mf_stream_cfg& c, StreamRes* r, std::string& err) = 0;
   virtual void close_stream(StreamRes* r) = 0;
@@ -62,6 +65,12 @@ class Executor {
                               std::string& err) = 0;
   virtual mf_status copy_maps(const mf_stream_cfg& c, StreamRes* r, int64_t frame, int n, float* dst,
                               bool device_dst, std::string& err) = 0;
+  // depth maps of n consecutive result slots (streams with emit_depth); executors without a depth
+  // head refuse
+  virtual mf_status copy_depth(const mf_stream_cfg&, StreamRes*, int64_t, int, float*, bool, std::string& err) {
+    err = "depth maps are not supported by this executor";
+    return MF_EINVAL;
+  }
   // op-level access used by the test/benchmark entry points
   virtual mf_status forward_frames(const float* frames_dev, int S, int H, int W, float* pose9_host,
                                    double* T_host, int max_layers, float* tokens_host,

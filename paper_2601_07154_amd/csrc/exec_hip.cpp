@@ -28,6 +28,8 @@ namespace mf {
   } while (0)
 
 static constexpr int KP = 640;     // patch length 3*14*14 = 588 padded to the GEMM k-tile
+static constexpr int DEPTH_OUT = 196;   // depth head outputs per patch token (its 14 x 14 pixels)
+static constexpr int DEPTH_N = 256;     // ... padded to a GEMM tile width
 
 static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -65,6 +67,7 @@ class HipExecutor : public Executor {
     if (F_ <= 0 || F_ % 128) { err = "mlp must be a positive multiple of 128"; return MF_EINVAL; }
     // MF_FP8: the QKV and MLP GEMMs take E4M3 operands; everything else runs as in MF_BF16
     fp8_ = m.precision == MF_FP8;
+    depth_head_ = m.depth_head != 0;
     dt_ = m.precision == MF_FP32 ? DT_F32 : DT_BF16;
     es_ = dt_ == DT_BF16 ? 2 : 4;
     qt_ = attention_q_tile(dt_, hd_);
@@ -108,14 +111,19 @@ class HipExecutor : public Executor {
 
   uint64_t stream_bytes(const mf_stream_cfg& c, int ring_cap, int map_cap, int hist_n) const override {
     const uint64_t hw = (uint64_t)c.height * c.width;
-    return (uint64_t)ring_cap * 3 * hw * 4 + (uint64_t)map_cap * hw * 4 + (uint64_t)hist_n * sizeof(FrameHist);
+    const uint64_t rings = (c.emit_maps ? 1 : 0) + (c.emit_depth ? 1 : 0);
+    return (uint64_t)ring_cap * 3 * hw * 4 + rings * map_cap * hw * 4 + (uint64_t)hist_n * sizeof(FrameHist);
   }
 
   mf_status open_stream(const mf_stream_cfg& c, StreamRes* r, std::string& err) override {
     HIPCHECK(hipSetDevice(device_));
     const uint64_t hw = (uint64_t)c.height * c.width;
     HIPCHECK(dmalloc(&r->ring, (size_t)r->ring_cap * 3 * hw * 4));
-    if (r->map_cap > 0) HIPCHECK(dmalloc(&r->maps, (size_t)r->map_cap * hw * 4));
+    if (r->map_cap > 0 && c.emit_maps) HIPCHECK(dmalloc(&r->maps, (size_t)r->map_cap * hw * 4));
+    if (r->map_cap > 0 && c.emit_depth) {
+      if (!depth_head_) { err = "emit_depth needs a model with a depth head"; return MF_EINVAL; }
+      HIPCHECK(dmalloc(&r->depth, (size_t)r->map_cap * hw * 4));
+    }
     HIPCHECK(dmalloc(&r->hist, (size_t)r->hist_n * sizeof(FrameHist)));
     HIPCHECK(hipMemsetAsync(r->hist, 0, (size_t)r->hist_n * sizeof(FrameHist), copy_));
     HIPCHECK(hipMemsetAsync(r->ring, 0, (size_t)r->ring_cap * 3 * hw * 4, copy_));
@@ -127,8 +135,9 @@ class HipExecutor : public Executor {
     hipSetDevice(device_);
     dfree(r->ring);
     dfree(r->maps);
+    dfree(r->depth);
     dfree(r->hist);
-    r->ring = r->maps = r->hist = nullptr;
+    r->ring = r->maps = r->depth = r->hist = nullptr;
   }
 
   mf_status upload_frames(const mf_stream_cfg& c, StreamRes* r, int64_t first, const float* src, int n,
@@ -160,6 +169,18 @@ class HipExecutor : public Executor {
     return MF_OK;
   }
 
+  mf_status copy_depth(const mf_stream_cfg& c, StreamRes* r, int64_t frame, int n, float* dst, bool device_dst,
+                       std::string& err) override {
+    HIPCHECK(hipSetDevice(device_));
+    if (!r->depth) { err = "the stream keeps no depth maps"; return MF_EINVAL; }
+    const size_t mb = (size_t)c.height * c.width * 4;
+    const int slot = (int)(frame % r->map_cap);
+    HIPCHECK(hipMemcpyAsync(dst, (char*)r->depth + (size_t)slot * mb, (size_t)n * mb,
+                            device_dst ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, copy_));
+    HIPCHECK(hipStreamSynchronize(copy_));
+    return MF_OK;
+  }
+
   mf_status run_batch(const Batch& b, std::vector<mf_focus>& out, double* gpu_ms, std::string& err) override {
     HIPCHECK(hipSetDevice(device_));
     latch_profiling();
@@ -177,6 +198,27 @@ class HipExecutor : public Executor {
     int32_t pose_rows = 0;
     for (size_t i = 0; i < b.wins.size(); ++i)
       if (b.wins[i].poses) { loc_off[i] = fwd_frames + pose_rows; pose_rows += b.wins[i].size; }
+    // depth targets of the forward frames, in the order add_window listed them
+    std::vector<DepthFrame> dframes;
+    bool has_depth = false;
+    for (size_t i = 0; i < b.wins.size(); ++i) {
+      const BatchWindow& w = b.wins[i];
+      if (w.poses) continue;
+      const size_t hw = (size_t)w.cfg->height * w.cfg->width;
+      for (int j = 0; j < w.size; ++j) {
+        const int64_t t = w.start + j;
+        DepthFrame df{};
+        if (w.cfg->emit_depth && w.res->depth && t >= w.emit_begin && t < w.emit_end) {
+          df.dst = (float*)w.res->depth + (size_t)(t % w.res->map_cap) * hw;
+          has_depth = true;
+        }
+        df.W = w.cfg->width;
+        df.gw = w.cfg->width / 14;
+        df.pe_base = w.res->pe_base;
+        df.win = (int32_t)i;
+        dframes.push_back(df);
+      }
+    }
     if (p.mtot > mcap_ || fwd_frames + pose_rows > fcap_) { err = "batch exceeds the workspace"; return MF_EINVAL; }
 
     // ---- chain / focus / map tables
@@ -246,6 +288,7 @@ class HipExecutor : public Executor {
     const size_t o_cwins = reserve(cwins.size() * sizeof(ChainWin));
     const size_t o_jobs = reserve(jobs.size() * sizeof(MapJob));
     const size_t o_poses = reserve((size_t)pose_rows * 16 * sizeof(double));
+    const size_t o_dframes = reserve(dframes.size() * sizeof(DepthFrame));
     mf_status rc = ensure_tables(off, err);
     if (rc != MF_OK) return rc;
     auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) memcpy(tab_host_ + o, src, bytes); };
@@ -259,6 +302,7 @@ class HipExecutor : public Executor {
     put(o_groups, groups.data(), groups.size() * sizeof(ChainGroup));
     put(o_cwins, cwins.data(), cwins.size() * sizeof(ChainWin));
     put(o_jobs, jobs.data(), jobs.size() * sizeof(MapJob));
+    put(o_dframes, dframes.data(), dframes.size() * sizeof(DepthFrame));
     {
       size_t po = o_poses;
       for (const BatchWindow& w : b.wins)
@@ -279,7 +323,18 @@ class HipExecutor : public Executor {
         HIPCHECK(hipMemcpyAsync(tloc_ + (size_t)fwd_frames * 16, T(o_poses), (size_t)pose_rows * 16 * sizeof(double),
                                 hipMemcpyDeviceToDevice, st_));
       HIPCHECK(chain_focus((const ChainGroup*)T(o_groups), (int)groups.size(), (const ChainWin*)T(o_cwins),
-                           (const StreamDev*)T(o_sdev), tloc_, pose9_, res_, st_));
+                           (const StreamDev*)T(o_sdev), tloc_, pose9_, res_, win_scale_, st_));
+      if (has_depth) {
+        // depth maps of the emitted frames from the last block's tokens, times their window's scale
+        prof_begin();
+        HIPCHECK(layernorm(dt_, X_, Y_, lnd_g_, lnd_b_, p.mtot, D_, nullptr, st_));
+        GemmArgs d{};
+        d.A = Y_; d.lda = D_; d.Bt = Wd_; d.ldb = D_; d.M = (int)p.mtot; d.N = DEPTH_N; d.K = D_; d.bias = bd_;
+        d.rowinfo = rowinfo_; d.rowframe = rowframe_; d.dframes = (const DepthFrame*)T(o_dframes);
+        d.win_scale = win_scale_;
+        HIPCHECK(gemm(dt_, EPI_DEPTH, d, st_));
+        prof_end(MF_STAGE_HEAD);
+      }
       HIPCHECK(focus_maps((const MapJob*)T(o_jobs), (int)jobs.size(), max_h, max_w, (const StreamDev*)T(o_sdev),
                           res_, keys_, psum_, st_));
       HIPCHECK(hipMemcpyAsync(res_host_, res_, (size_t)out_n * sizeof(mf_focus), hipMemcpyDeviceToHost, st_));
@@ -292,9 +347,10 @@ class HipExecutor : public Executor {
       // the token rows, the frames and work lists, the windows and the largest of them (the fp8
       // window quantiser's grid), the chain and map tables, the poses and the records.
       char sig[256];
-      snprintf(sig, sizeof sig, "%lld/%d/%zu/%zu/%zu/%zu/%d/%zu/%zu/%zu/%d/%d/%d/%d/%d/%zu", (long long)p.mtot,
+      snprintf(sig, sizeof sig, "%lld/%d/%zu/%zu/%zu/%zu/%d/%zu/%zu/%zu/%d/%d/%d/%d/%d/%zu/%d", (long long)p.mtot,
                p.max_npad, p.frames.size(), p.fwork.size(), p.gwork.size(), p.gsegs.size(), p.max_rows,
-               groups.size(), cwins.size(), jobs.size(), max_h, max_w, pose_rows, fwd_frames, out_n, off);
+               groups.size(), cwins.size(), jobs.size(), max_h, max_w, pose_rows, fwd_frames, out_n, off,
+               has_depth ? 1 : 0);
       auto it = graphs_.find(sig);
       if (it == graphs_.end()) {
         if (graphs_.size() >= 64) clear_graphs();
@@ -433,17 +489,18 @@ class HipExecutor : public Executor {
   size_t expected_floats() const {
     const size_t D = D_, F = F_;
     return 588 * D + 3 * D + depth_ * (2 * D + D * 3 * D + 3 * D + D * D + D + 2 * D + D * F + F + F * D + D) +
-           2 * D + D * D + D + D * 9 + 9;
+           2 * D + D * D + D + D * 9 + 9 + (depth_head_ ? 2 * D + D * DEPTH_OUT + DEPTH_OUT : 0);
   }
   uint64_t weight_bytes() const {
     const uint64_t D = D_, F = F_;
-    return expected_floats() * 4 + (D * KP + depth_ * (3 * D * D + D * D + 2 * D * F)) * es_ + D * D * 4;
+    return expected_floats() * 4 + (D * KP + depth_ * (3 * D * D + D * D + 2 * D * F)) * es_ + D * D * 4 +
+           (depth_head_ ? (uint64_t)DEPTH_N * D * es_ + DEPTH_N * 4 : 0);
   }
   uint64_t workspace_bytes() const {
     const uint64_t D = D_, wide = std::max<int64_t>(F_, KP);
     const uint64_t f8 = fp8_ ? (uint64_t)mcap_ * (D + F_ + 8) : 0;
-    return f8 + (uint64_t)mcap_ * (D * 4 + D * es_ + D * es_ + wide * es_ + 4) + (uint64_t)mpad_ * 3 * D * es_ +
-           (uint64_t)fcap_ * (2 * D * 4 + 9 * 4 + 16 * 8 + sizeof(mf_focus) * 2 + 8) + (64u << 20);
+    return f8 + (uint64_t)mcap_ * (D * 4 + D * es_ + D * es_ + wide * es_ + 4 + 4) + (uint64_t)mpad_ * 3 * D * es_ +
+           (uint64_t)fcap_ * (2 * D * 4 + 9 * 4 + 16 * 8 + sizeof(mf_focus) * 2 + 8 + 8) + (64u << 20);
   }
 
   // ------------------------------------------------------------------ weights
@@ -500,6 +557,18 @@ class HipExecutor : public Executor {
     h_2_ = take(9);
     HIPCHECK(dmalloc(&H1t_, D * D * 4));
     HIPCHECK(convert_transpose(DT_F32, H1, (int)D, (int)D, H1t_, (int)D, st_));
+    if (depth_head_) {
+      // depth head: W_d [D][196] transposed to [256][D] (rows 196.. zero), bias padded to 256
+      lnd_g_ = take(D); lnd_b_ = take(D);
+      const float* Wd = take(D * DEPTH_OUT);
+      const float* bd = take(DEPTH_OUT);
+      HIPCHECK(dmalloc(&Wd_, (size_t)DEPTH_N * D * es_));
+      HIPCHECK(hipMemsetAsync(Wd_, 0, (size_t)DEPTH_N * D * es_, st_));
+      HIPCHECK(convert_transpose(dt_, Wd, (int)D, DEPTH_OUT, Wd_, (int)D, st_));
+      HIPCHECK(dmalloc(&bd_, DEPTH_N * 4));
+      HIPCHECK(hipMemsetAsync(bd_, 0, DEPTH_N * 4, st_));
+      HIPCHECK(hipMemcpyAsync(bd_, bd, DEPTH_OUT * 4, hipMemcpyDeviceToDevice, st_));
+    }
     HIPCHECK(hipStreamSynchronize(st_));
     return MF_OK;
   }
@@ -511,6 +580,8 @@ class HipExecutor : public Executor {
     HIPCHECK(dmalloc(&O_, (size_t)mcap_ * D * es_));
     HIPCHECK(dmalloc(&Hb_, (size_t)mcap_ * wide * es_));
     HIPCHECK(dmalloc(&rowinfo_, (size_t)mcap_ * 4));
+    HIPCHECK(dmalloc(&rowframe_, (size_t)mcap_ * 4));
+    HIPCHECK(dmalloc(&win_scale_, (size_t)fcap_ * 8));
     HIPCHECK(dmalloc(&Q_, (size_t)mpad_ * D * es_));
     HIPCHECK(dmalloc(&K_, (size_t)mpad_ * D * es_));
     HIPCHECK(dmalloc(&Vt_, (size_t)mpad_ * D * es_));
@@ -628,7 +699,7 @@ class HipExecutor : public Executor {
                     const AttnSeg* gsegs, const AttnWork* gwork, const int32_t* cam_rows, int layers,
                     std::string& err) {
     const int M = (int)p.mtot, D = D_;
-    HIPCHECK(im2col(dt_, frames, (int)p.frames.size(), p.max_npad, Hb_, KP, rowinfo_, st_));
+    HIPCHECK(im2col(dt_, frames, (int)p.frames.size(), p.max_npad, Hb_, KP, rowinfo_, rowframe_, st_));
     GemmArgs g{};
     g.A = Hb_; g.lda = KP; g.Bt = Wp_; g.ldb = KP; g.M = M; g.N = D; g.K = KP;
     g.bias = b_p_; g.C = X_; g.ldc = D; g.N = D;
@@ -777,7 +848,8 @@ class HipExecutor : public Executor {
     auto F = [this](void* p) { dfree(p); };
     F(wdev_); F(Wp_); F(H1t_);
     for (auto& L : layers_) { F(L.Wqkv); F(L.Wo); F(L.W1); F(L.W2); }
-    F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(Q_); F(K_); F(Vt_);
+    F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(rowframe_); F(win_scale_); F(Q_); F(K_); F(Vt_);
+    F(Wd_); F(bd_);
     F(Y8_); F(H8_); F(srow_); F(srow2_); F(amax_); F(wscale_); F(wamax_);
     F(camln_); F(camg_); F(pose9_); F(tloc_); F(res_); F(keys_); F(psum_); F(pe_); F(tab_dev_);
     if (res_host_) hipHostFree(res_host_);
@@ -829,6 +901,12 @@ class HipExecutor : public Executor {
   float* X_ = nullptr;
   void *Y_ = nullptr, *O_ = nullptr, *Hb_ = nullptr, *Q_ = nullptr, *K_ = nullptr, *Vt_ = nullptr;
   int32_t* rowinfo_ = nullptr;
+  int32_t* rowframe_ = nullptr;    // token row -> frame index of the batch (im2col)
+  double* win_scale_ = nullptr;    // per chained window: the anchoring's translation scale factor
+  bool depth_head_ = false;
+  const float *lnd_g_ = nullptr, *lnd_b_ = nullptr;
+  void* Wd_ = nullptr;             // depth head [DEPTH_N][D], compute type, rows >= DEPTH_OUT zero
+  float* bd_ = nullptr;            // [DEPTH_N]
   float *camln_ = nullptr, *camg_ = nullptr, *pose9_ = nullptr;
   double* tloc_ = nullptr;
   mf_focus* res_ = nullptr;

@@ -77,7 +77,36 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
     if (which == 0 && a.qscale != 0.0f) qs = a.qscale;
   }
   static_assert(WN % 2 == 0, "the staged epilogue takes a wave's columns 64 at a time");
-  if constexpr (EPI == EPI_PATCH) {
+  if constexpr (EPI == EPI_DEPTH) {
+    // depth maps: a lane holds one token row and 4 consecutive columns per register group; patch
+    // rows of frames with a target write scale * exp(value) to the pixel of each column < 196
+    static_assert(TC == 1, "depth rows are row-major tiles");
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      const int m = m0 + wr * 32 * WM + i * 32 + l32;
+      if (m >= a.M) continue;
+      const int32_t ri = a.rowinfo[m];
+      if ((ri >> 30) & 3) continue;                      // camera token or padding row
+      const DepthFrame df = a.dframes[a.rowframe[m]];
+      if (!df.dst) continue;                             // frame not emitted by this window
+      const int p = (ri & 0x3fffffff) - df.pe_base;
+      const int py = p / df.gw, px = p - py * df.gw;
+      const float sc = (float)a.win_scale[df.win];
+      float* base = df.dst + (int64_t)(py * 14) * df.W + px * 14;
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int n = n0 + wc * 32 * WN + j * 32 + 8 * rg + 4 * g + e;
+            if (n < 196) {
+              const int ky = n / 14, kx = n - ky * 14;
+              base[(int64_t)ky * df.W + kx] = sc * expf(acc[i][j][4 * rg + e] + a.bias[n]);
+            }
+          }
+    }
+  } else if constexpr (EPI == EPI_PATCH) {
     // once per batch: direct stores. rowinfo bits 30-31: 0 patch, 1 reference camera, 2 other
     // camera, 3 padding; low bits the position-code row
 #pragma unroll
@@ -494,13 +523,14 @@ static hipError_t dispatch(Epi epi, const GemmArgs& a, hipStream_t s) {
     case EPI_QKV: return launch<T, EPI_QKV>(a, s);
     case EPI_PATCH: return launch<T, EPI_PATCH>(a, s);
     case EPI_STORE: return launch<T, EPI_STORE>(a, s);
+    case EPI_DEPTH: return launch<T, EPI_DEPTH>(a, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t gemm(Dtype dt, Epi epi, const GemmArgs& a, hipStream_t s) {
   if (dt == DT_FP8) {
-    if (epi == EPI_PATCH || epi == EPI_STORE) return hipErrorInvalidValue;   // not used with fp8
+    if (epi == EPI_PATCH || epi == EPI_STORE || epi == EPI_DEPTH) return hipErrorInvalidValue;   // not used with fp8
     if (!a.ascale || !a.bscale) return hipErrorInvalidValue;
     return dispatch<fp8>(epi, a, s);
   }

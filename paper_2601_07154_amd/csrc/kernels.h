@@ -8,7 +8,14 @@ namespace mf {
 enum Dtype { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };   // DT_FP8: OCP E4M3 bytes
 
 // ---------------------------------------------------------------- GEMM  C = A Bt^T (+ epilogue)
-enum Epi { EPI_RESID = 1, EPI_GELU = 2, EPI_QKV = 3, EPI_PATCH = 4, EPI_STORE = 5 };
+enum Epi { EPI_RESID = 1, EPI_GELU = 2, EPI_QKV = 3, EPI_PATCH = 4, EPI_STORE = 5, EPI_DEPTH = 6 };
+
+// EPI_DEPTH: one frame of a batch whose patch rows are written as a depth map
+struct DepthFrame {
+  float* dst;                      // [H][W] fp32 depth map of the frame, or null (frame not emitted)
+  int32_t W, gw, pe_base;          // width, patch-grid width, first position-code row of its resolution
+  int32_t win;                     // its window's index in the chain table (scale factor win_scale[win])
+};
 
 struct GemmArgs {
   const void* A; int64_t lda;      // [M, K] row-major, dtype
@@ -24,6 +31,10 @@ struct GemmArgs {
   const float* ascale; const float* bscale;
   // EPI_PATCH: per-row kind/PE row (rowinfo), PE table [rows][N] fp32, camera tokens
   const int32_t* rowinfo; const float* pe; const float* c_ref; const float* c_other;
+  // EPI_DEPTH: rowinfo as above, each row's frame in the batch, the frames' targets, and the windows'
+  // scale factors; C = depth maps: dst[(14 py + n / 14) W + 14 px + n % 14] = scale exp(acc + bias)
+  // for output columns n < 196 of a patch row (py, px)
+  const int32_t* rowframe; const DepthFrame* dframes; const double* win_scale;
 };
 hipError_t gemm(Dtype dt, Epi epi, const GemmArgs& a, hipStream_t s);
 
@@ -55,9 +66,10 @@ struct FrameDesc {
   int32_t first;          // 1 for the first frame of its window (reference camera token)
   int32_t pe_base;        // first row of the frame's resolution in the PE arena
 };
-// Writes the normalised patch matrix A [rows, kpad] (dtype) and rowinfo for every token row.
+// Writes the normalised patch matrix A [rows, kpad] (dtype), rowinfo and (if not null) rowframe
+// (the row's frame index in `frames`) for every token row.
 hipError_t im2col(Dtype dt, const FrameDesc* frames, int nframes, int max_npad, void* A, int kpad,
-                  int32_t* rowinfo, hipStream_t s);
+                  int32_t* rowinfo, int32_t* rowframe, hipStream_t s);
 hipError_t make_pe(float* pe, int gh, int gw, int dim, hipStream_t s);
 
 // ---------------------------------------------------------------- weights
@@ -115,10 +127,11 @@ struct ChainGroup { int32_t first_win, n_win; };   // the windows of one stream,
 
 struct MapJob { int32_t stream, out; int64_t frame; };
 
-// T_loc [rows][16] fp64 local poses, pose9 [rows][9] (nullable); out: result records.
+// T_loc [rows][16] fp64 local poses, pose9 [rows][9] (nullable); out: result records; win_scale
+// (nullable): [nwins] each window's translation scale factor (MF_ANCHOR_YAW_SCALE, else 1).
 hipError_t chain_focus(const ChainGroup* groups, int ngroups, const ChainWin* wins,
                        const StreamDev* streams, const double* T_loc, const float* pose9,
-                       mf_focus* out, hipStream_t s);
+                       mf_focus* out, double* win_scale, hipStream_t s);
 // Rows of the map one render workgroup covers; the sum normaliser takes one partial per workgroup.
 constexpr int MAP_ROWS = 8;
 inline int map_row_blocks(int max_h) { return (max_h + MAP_ROWS - 1) / MAP_ROWS; }

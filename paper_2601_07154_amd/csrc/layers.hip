@@ -70,12 +70,14 @@ hipError_t layernorm(Dtype out_dt, const float* x, void* y, const float* g, cons
 template <typename T>
 __global__ __launch_bounds__(256) void im2col_kernel(const FrameDesc* __restrict__ frames,
                                                      T* __restrict__ A, int kpad,
-                                                     int32_t* __restrict__ rowinfo) {
+                                                     int32_t* __restrict__ rowinfo,
+                                                     int32_t* __restrict__ rowframe) {
   const FrameDesc fd = frames[blockIdx.y];
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= fd.npad) return;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)fd.token_base + j;
+  if (rowframe && lane == 0) rowframe[row] = (int32_t)blockIdx.y;
   T* ar = A + row * kpad;
   if (j == 0 || j > fd.P) {
     for (int k = lane; k < kpad; k += 64) ar[k] = from_f32<T>(0.0f);
@@ -99,13 +101,13 @@ __global__ __launch_bounds__(256) void im2col_kernel(const FrameDesc* __restrict
 }
 
 hipError_t im2col(Dtype dt, const FrameDesc* frames, int nframes, int max_npad, void* A, int kpad,
-                  int32_t* rowinfo, hipStream_t s) {
+                  int32_t* rowinfo, int32_t* rowframe, hipStream_t s) {
   if (nframes <= 0) return hipSuccess;
   const dim3 grid((unsigned)((max_npad + 3) / 4), (unsigned)nframes);
   if (dt == DT_BF16)
-    hipLaunchKernelGGL((im2col_kernel<bf16>), grid, dim3(256), 0, s, frames, (bf16*)A, kpad, rowinfo);
+    hipLaunchKernelGGL((im2col_kernel<bf16>), grid, dim3(256), 0, s, frames, (bf16*)A, kpad, rowinfo, rowframe);
   else
-    hipLaunchKernelGGL((im2col_kernel<float>), grid, dim3(256), 0, s, frames, (float*)A, kpad, rowinfo);
+    hipLaunchKernelGGL((im2col_kernel<float>), grid, dim3(256), 0, s, frames, (float*)A, kpad, rowinfo, rowframe);
   return hipGetLastError();
 }
 

@@ -65,7 +65,8 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
                                                          const StreamDev* __restrict__ streams,
                                                          const double* __restrict__ T_loc,
                                                          const float* __restrict__ pose9,
-                                                         mf_focus* __restrict__ out) {
+                                                         mf_focus* __restrict__ out,
+                                                         double* __restrict__ win_scale) {
   __shared__ double A[16];
   __shared__ double rho;   // scale of the window's translations (MF_ANCHOR_YAW_SCALE), else 1
   const ChainGroup gr = groups[blockIdx.x];
@@ -106,6 +107,7 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
       } else {
         for (int i = 0; i < 16; ++i) A[i] = (i % 5 == 0) ? 1.0 : 0.0;
       }
+      if (win_scale) win_scale[wi] = rho;
     }
     __syncthreads();
     const int64_t n_emit = w.emit_end - w.emit_begin;
@@ -180,10 +182,10 @@ __global__ __launch_bounds__(64) void chain_focus_kernel(const ChainGroup* __res
 
 hipError_t chain_focus(const ChainGroup* groups, int ngroups, const ChainWin* wins,
                        const StreamDev* streams, const double* T_loc, const float* pose9,
-                       mf_focus* out, hipStream_t s) {
+                       mf_focus* out, double* win_scale, hipStream_t s) {
   if (ngroups <= 0) return hipSuccess;
   hipLaunchKernelGGL(chain_focus_kernel, dim3(ngroups), dim3(64), 0, s, groups, wins, streams,
-                     T_loc, pose9, out);
+                     T_loc, pose9, out, win_scale);
   return hipGetLastError();
 }
 

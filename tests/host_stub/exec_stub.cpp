@@ -32,7 +32,8 @@ class StubExecutor : public Executor {
   int rows_per_frame(int H, int W) const override { return ((H / 14) * (W / 14) + 1 + 7) / 8 * 8; }
   uint64_t stream_bytes(const mf_stream_cfg& c, int ring_cap, int map_cap, int hist_n) const override {
     const uint64_t hw = (uint64_t)c.height * c.width;
-    return (uint64_t)ring_cap * 3 * hw * 4 + (uint64_t)map_cap * hw * 4 + (uint64_t)hist_n * 168;
+    const uint64_t rings = (c.emit_maps ? 1 : 0) + (c.emit_depth ? 1 : 0);
+    return (uint64_t)ring_cap * 3 * hw * 4 + rings * map_cap * hw * 4 + (uint64_t)hist_n * 168;
   }
   // Shared state as the device executor has it: a per-resolution table that stream opens extend
   // (opens run on API threads, outside the engine lock) and a profiling switch that API threads

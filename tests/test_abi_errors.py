@@ -116,3 +116,18 @@ def test_engine_create_rejects_bad_models(lib, change):
     st = lib.mf_engine_create(C.byref(m), C.c_void_p(blob.ctypes.data), n, C.byref(rt), C.byref(h))
     assert st == _lib.MF_EINVAL and not h.value
     assert lib.mf_last_error().decode()
+
+
+@pytest.mark.parametrize("flag,extra", [(1, 0), (0, 1)])
+def test_engine_create_checks_the_depth_head_blob(lib, flag, extra):
+    """A model with the depth head needs its tensors at the end of the blob and one without refuses
+    them (checked before the device is touched)."""
+    from paper_2601_07154_amd import _lib
+    head = mf_synth.ModelConfig(2, 128, 2, 256, depth_head=bool(extra))
+    blob = mf_synth.make_weights(head, 0)
+    m = _lib.ModelCfg(2, 128, 2, 256, 14, _lib.MF_BF16, flag)
+    rt = _lib.RuntimeCfg(0, 0, 0, 0, None, 0, 0)
+    h = C.c_void_p()
+    st = lib.mf_engine_create(C.byref(m), C.c_void_p(blob.ctypes.data), blob.size, C.byref(rt), C.byref(h))
+    assert st == _lib.MF_EINVAL and not h.value
+    assert "floats" in lib.mf_last_error().decode()
