@@ -303,16 +303,21 @@ def run_serve(args):
     K = lambda H, W: (0.8 * W, 0.8 * W, W / 2.0, H / 2.0)
     rows = mfp.rows_per_frame(504, 504)
     eng = mfp.Engine.from_model(model, blob, precision="bf16", threaded=True, max_tokens=6 * 16 * rows)
-    out = serving.serve(eng, specs, pool, 16, 8, K, fps=30.0, paced=args.serve_paced, time_limit=900)
+    report = lambda d: print(f"[serve] {d['t']:.0f} s: {d['admitted']} admitted, {d['active']} active, "
+                             f"{d['done']} done, {d['frames']} frames", file=sys.stderr, flush=True)
+    out = serving.serve(eng, specs, pool, 16, 8, K, fps=30.0, paced=args.serve_paced, time_limit=args.serve_time_limit,
+                        progress=report)
     st = eng.stats()
     eng.close()
-    lat = serving.latency_summary(out["records"])
+    # paced: latency from each frame's capture time (admission wait included); unpaced: from its push
+    lat = serving.latency_summary(out["records"], out["waits"] if args.serve_paced else None)
     frames = lat["frames"]
     res = {"metric": "serving frames/sec and per-frame latency (BF16, continuous batching) vs FP32 single-stream",
            "value": frames / out["wall"], "unit": "frames/s", "n_gpus": 1, "dtype": "bf16",
            "regime": "paced 30 fps, Poisson arrivals" if args.serve_paced else "throughput (all frames available)",
            "streams": len(specs), "frames": frames, "wall_s": out["wall"], "latency_ms": lat,
            "batches": st["batches_run"], "windows": st["windows_run"], "gpu_ms": st["gpu_ms"],
+           "admission_refusals": int(sum(out["refused"])), "max_streams_open": out["max_active"],
            "config": {"workload": "serving", "model": "24L D1024 16 heads MLP 4096", "window": 16, "overlap": 8,
                       "lengths": f"U[60, {args.serve_max_len}]", "resolutions": "{280,378,504}x504",
                       "rate_per_s": args.serve_rate}}
@@ -355,6 +360,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.4)
     ap.add_argument("--serve-paced", action="store_true")
     ap.add_argument("--serve-fp32-streams", type=int, default=2)
+    ap.add_argument("--serve-time-limit", type=float, default=900.0)
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())

@@ -46,21 +46,31 @@ class StreamState:
 
 def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float = 30.0,
           paced: bool = True, poll_cap: int = 256, time_limit: float = 600.0, sigma: float = 1000.0,
-          emit_maps: bool = False, push_chunk: int = 1):
+          emit_maps: bool = False, push_chunk: int = 1, progress=None, progress_every: float = 30.0):
     """Run the streams to completion on a threaded engine.
 
     frame_pool(height, width) -> array/tensor [P, 3, H, W] of frames pushed cyclically.
-    K_of(height, width) -> intrinsics.  Returns dict(records per stream, wall seconds, stats).
+    K_of(height, width) -> intrinsics.  progress(dict) is called every progress_every seconds with
+    the run's counts.  Returns dict(records per stream, wall seconds, stats, states; per stream:
+    admitted_at and the number of MF_EAGAIN refusals of its admission).
     """
     states = [StreamState(s) for s in specs]
     pending = list(range(len(states)))          # not yet admitted, in arrival order
     active = []
     t0 = time.perf_counter()
     pools = {}
+    refused = [0] * len(states)
+    max_active = 0
+    next_report = progress_every
     while True:
         now = time.perf_counter() - t0
         if now > time_limit:
             raise TimeoutError("serving run exceeded its time limit")
+        if progress is not None and now >= next_report:
+            next_report += progress_every
+            progress({"t": now, "admitted": len(states) - len(pending), "active": len(active),
+                      "done": sum(st.done for st in states),
+                      "frames": sum(sum(len(r) for r in st.records) for st in states)})
         # admission in arrival order
         while pending and states[pending[0]].spec.arrival <= now:
             st = states[pending[0]]
@@ -69,11 +79,13 @@ def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float
                                      emit_maps=emit_maps, ring_frames=2 * window + 8 * push_chunk,
                                      allow_again=True)
             if sid < 0:
+                refused[pending[0]] += 1
                 break                            # budget held by other streams: retry later
             st.sid = sid
             st.admitted_at = now
             active.append(st)
             pending.pop(0)
+            max_active = max(max_active, len(active))
         # pushes: frames whose capture time (arrival + i / fps) has come (paced), or everything
         # (throughput regime)
         for st in active:
@@ -114,7 +126,8 @@ def serve(engine, specs, frame_pool, window: int, overlap: int, K_of, fps: float
     wall = time.perf_counter() - t0
     recs = [np.concatenate(st.records) if st.records else np.zeros(0) for st in states]
     waits = [np.asarray(st.wait, dtype=np.float64) for st in states]
-    return dict(records=recs, waits=waits, wall=wall, stats=engine.stats(), states=states)
+    return dict(records=recs, waits=waits, wall=wall, stats=engine.stats(), states=states, refused=refused,
+                admitted_at=[st.admitted_at for st in states], max_active=max_active)
 
 
 def latency_summary(recs_list, waits=None):
