@@ -441,6 +441,14 @@ def main():
         e8 = golden_errors(wl, inp, f8["first"])
         if e8 is not None:
             res["error_vs_fp64_oracle_fp8"] = e8
+        # stage timing of the fp8 precision (a short eager run with events)
+        p8 = run_gpu(inp, "fp8", 2, 1, profile=True, graphs=False)
+        st8 = p8["stages"]
+        res["fp8_stage_ms_per_step"] = {k: v[0] / 2 for k, v in st8.items() if v[1]}
+        g8 = sum(st8[k][0] for k in GEMM_STAGES) / 2
+        gb = sum(stages[k][0] for k in GEMM_STAGES) / args.steps
+        if g8 > 0 and gb > 0:
+            res["fp8_gemm_speedup_vs_bf16"] = gb / g8
     if not args.no_fp32 and args.precision != "fp32":
         v32, dt32, st32 = run_fp32_single_stream(inp)
         res["fp32_single_stream"] = {"value": v32, "unit": "frames/s", "seconds": dt32,
