@@ -28,7 +28,13 @@ Options
                     window and each weight matrix are divided by their own
                     per-tensor scale amax/448, rounded to E4M3 (nearest even,
                     saturating), and the product is multiplied back by both
-                    scales.  Also a calibration, not a parity reference.
+                    scales; and the attention scores q k^T take E4M3 operands
+                    too: every query row (multiplied by log2(e)/sqrt(hd) in
+                    fp32) and every key row of a head is divided by its own
+                    power-of-two scale 2^e, e the smallest integer with
+                    448 * 2^e >= the row's amax, and rounded to E4M3, so the
+                    scores come out in base-2 exponent units; the probabilities
+                    and V stay bf16.  Also a calibration, not a parity reference.
 """
 from __future__ import annotations
 
@@ -75,6 +81,24 @@ def quantise_e4m3(x: np.ndarray) -> tuple[np.ndarray, float]:
     amax = float(np.max(np.abs(x))) if np.size(x) else 0.0
     s = amax / E4M3_MAX if amax > 0.0 else 1.0
     return round_e4m3(np.asarray(x, dtype=np.float64) / s), s
+
+
+def pow2_row_scale(amax: np.ndarray) -> np.ndarray:
+    """Per row: the smallest integer e with 448 * 2^e >= amax (amax > 0), as float64; 0 for a zero row."""
+    a = np.asarray(amax, dtype=np.float64)
+    e = np.ceil(np.log2(np.where(a > 0, a, E4M3_MAX) / E4M3_MAX))
+    # guard the logarithm's last bit: move e to the exact boundary
+    e = np.where(E4M3_MAX * 2.0 ** (e - 1) >= a, e - 1, e)
+    e = np.where(E4M3_MAX * 2.0 ** e < a, e + 1, e)
+    return np.where(a > 0, e, 0.0)
+
+
+def quantise_rows_e4m3(x: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Per-row power-of-two scaling: q = E4M3(x / 2^e) with e = pow2_row_scale(row amax); returns
+    (q, e) so that x ~ q * 2^e row by row."""
+    x = np.asarray(x, dtype=np.float64)
+    e = pow2_row_scale(np.max(np.abs(x), axis=-1))
+    return round_e4m3(x / 2.0 ** e[..., None]), e
 
 
 class Prec:
@@ -189,8 +213,22 @@ def attention(q: np.ndarray, k: np.ndarray, v: np.ndarray, prec: Prec | None = N
     prec = prec or Prec()
     hd = q.shape[-1]
     scale = 1.0 / math.sqrt(hd)
-    kk, vv = prec.op(k), prec.op(v)
+    vv = prec.op(v)
     out = np.empty((q.shape[0], v.shape[1]), dtype=np.float64)
+    if prec.name == "fp8":
+        # scores on E4M3 operands with per-row power-of-two scales, in base-2 exponent units
+        c = np.float32(math.log2(math.e) / math.sqrt(hd))
+        qs = (np.asarray(q, dtype=np.float32) * c).astype(np.float64)
+        q8, eq = quantise_rows_e4m3(qs)
+        k8, ek = quantise_rows_e4m3(np.asarray(k, dtype=np.float32).astype(np.float64))
+        for s in range(0, q.shape[0], chunk):
+            sc = (q8[s:s + chunk] @ k8.T) * 2.0 ** (eq[s:s + chunk, None] + ek[None, :])
+            sc -= sc.max(axis=1, keepdims=True)
+            p = np.exp2(sc)
+            l = p.sum(axis=1, keepdims=True)
+            out[s:s + chunk] = (prec.op(p) @ vv) / l
+        return out
+    kk = prec.op(k)
     for s in range(0, q.shape[0], chunk):
         sc = (prec.op(q[s:s + chunk]) @ kk.T) * scale
         sc -= sc.max(axis=1, keepdims=True)

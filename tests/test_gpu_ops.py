@@ -10,7 +10,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("M,N,K", [(300, 256, 256), (1, 128, 640), (517, 384, 1536)])
+# (16400, 1024, 256): enough tiles for the 256 x 128 tile of the bf16 path, with a ragged last row block
+@pytest.mark.parametrize("M,N,K", [(300, 256, 256), (1, 128, 640), (517, 384, 1536), (16400, 1024, 256)])
 def test_gemm_small_integers_bit_exact(prec, M, N, K):
     torch = torch_cuda()
     m = mf()
@@ -18,7 +19,8 @@ def test_gemm_small_integers_bit_exact(prec, M, N, K):
     A = rng.integers(-3, 4, size=(M, K)).astype(np.float32)
     B = rng.integers(-3, 4, size=(N, K)).astype(np.float32)
     bias = rng.integers(-5, 6, size=N).astype(np.float32)
-    ref = (A.astype(np.int64) @ B.astype(np.int64).T + bias.astype(np.int64)).astype(np.float64)
+    # integer-valued float64 products and sums (|sum| <= 9 K + 5 < 2^53): exact
+    ref = A.astype(np.float64) @ B.astype(np.float64).T + bias.astype(np.float64)
     tdt = torch.bfloat16 if prec == "bf16" else torch.float32
     dA = torch.from_numpy(A).to("cuda", tdt).contiguous()
     dB = torch.from_numpy(B).to("cuda", tdt).contiguous()

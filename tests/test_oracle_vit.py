@@ -307,3 +307,57 @@ def test_fp8_mode_only_changes_qkv_and_mlp():
              + sub * sub * sa * sb * a.shape[1] + 1e-12)
     assert np.all(np.abs(p8.matmul_q(a, b) - ref) <= bound)
     assert not np.array_equal(p8.matmul_q(a, b), pb.matmul(a, b))
+
+
+def test_pow2_row_scale_is_the_smallest_power_of_two_that_fits():
+    """e is the least integer with 448 * 2^e >= amax: brute force over exponents, including amax on
+    and next to the boundaries 448 * 2^k and the zero row."""
+    rng = np.random.default_rng(31)
+    amax = np.concatenate([np.exp(rng.uniform(-40, 40, 500)),
+                           448.0 * 2.0 ** np.arange(-20, 21, dtype=np.float64),
+                           np.nextafter(448.0 * 2.0 ** np.arange(-20, 21, dtype=np.float64), np.inf),
+                           np.nextafter(448.0 * 2.0 ** np.arange(-20, 21, dtype=np.float64), 0.0)])
+    e = vit.pow2_row_scale(amax)
+    for a, ei in zip(amax, e):
+        ks = [k for k in range(-200, 200) if 448.0 * 2.0 ** k >= a]
+        assert ei == min(ks), (a, ei)
+    assert vit.pow2_row_scale(np.array([0.0]))[0] == 0.0
+
+
+def test_row_quantisation_decodes_within_e4m3_rounding():
+    """q * 2^e is x to within half an E4M3 quantum of x / 2^e, every |q| <= 448, and each non-zero row
+    reaches its top binade: max |x| / 2^e lies in (224, 448], so after rounding (quantum 16 below 256)
+    |q|max lies in [224, 448]."""
+    rng = np.random.default_rng(32)
+    x = rng.normal(0, 1, (64, 64)) * np.exp(rng.uniform(-8, 8, (64, 1)))
+    q, e = vit.quantise_rows_e4m3(x)
+    assert np.abs(q).max() <= 448.0
+    rowmax = np.abs(q).max(axis=1)
+    assert ((rowmax >= 224.0) & (rowmax <= 448.0)).all()
+    ratio = np.abs(x).max(axis=1) / 2.0 ** e
+    assert ((ratio > 224.0) & (ratio <= 448.0)).all()
+    y = x / 2.0 ** e[:, None]
+    a = np.maximum(np.abs(y), 2.0 ** -6)
+    half_quantum = 2.0 ** (np.floor(np.log2(a)) - 4)
+    assert (np.abs(q - y) <= half_quantum + 1e-300).all()
+
+
+def test_fp8_attention_emulation_against_exact_softmax():
+    """The fp8 emulation's scores are q k^T / sqrt(hd) (in base 2) up to the two E4M3 roundings: with
+    queries and keys exactly representable after scaling (small integers times a power of two) the
+    emulated attention equals the exact one up to the bf16 rounding of P and V."""
+    rng = np.random.default_rng(33)
+    hd = 64
+    c = np.float32(math.log2(math.e) / math.sqrt(hd))
+    # queries: integers / c so that q * c (fp32) lands on small integers -> exactly representable
+    k = rng.integers(-7, 8, (40, hd)).astype(np.float64)
+    v = rng.normal(0, 1, (40, hd))
+    qi = rng.integers(-3, 4, (9, hd)).astype(np.float64)
+    q = (qi.astype(np.float32) / c).astype(np.float64)
+    exactq = (np.asarray(q, np.float32) * c).astype(np.float64)
+    assert np.array_equal(exactq, qi) or np.abs(exactq - qi).max() < 1e-6
+    got = vit.attention(q, k, v, vit.Prec("fp8"))
+    s = (exactq @ k.T)
+    p = np.exp2(s - s.max(axis=1, keepdims=True))
+    want = (p @ v) / p.sum(axis=1, keepdims=True)
+    assert np.abs(got - want).max() < 2e-2 * np.abs(want).max()
