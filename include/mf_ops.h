@@ -37,7 +37,9 @@ mf_status mf_forward_window(mf_engine* e, const float* frames_dev, int32_t S, in
  * take), 3 K, 4 Vt (layouts above; mpad is max_tokens_per_batch rounded up to 8,
  * plus 256), 5 attention output O
  * ([rows][dim]), 6 MLP hidden / patch matrix ([rows][max(mlp, 640)]); element type T of the
- * engine's precision except X.  MF_EINVAL beyond the buffer. */
+ * engine's precision except X; MF_FP8 engines with head dim 64 also keep 7 the E4M3 queries and
+ * 8 keys ([heads][mpad][64] bytes) and 9, 10 their E8M0 row-scale bytes ([heads][mpad]).
+ * MF_EINVAL beyond the buffer or for a buffer the engine does not keep. */
 mf_status mf_debug_copy(mf_engine* e, int32_t which, void* host, size_t bytes);
 
 /* Per-kernel timing (HIP events on the engine's stream, summed over batches since the last
@@ -69,6 +71,16 @@ mf_status mf_profile_stages(mf_engine* e, double* ms, int64_t* calls, int32_t n)
 mf_status mf_op_attention(int32_t precision, int32_t head_dim, int32_t heads, int32_t dim,
                           const void* q, const void* k, const void* vt, void* o, int64_t mpad,
                           const int32_t* segs, int32_t nseg, void* stream);
+
+/* The attention of mf_op_attention with its scores on E4M3 operands (the MF_FP8 precision, head
+ * dim 64): q8, k8 [heads][mpad][64] E4M3 rows, qe, ke [heads][mpad] bytes: row r of head h stands for
+ * q8[h][r] * 2^(qe[h][r] - 127) (E8M0), the queries already multiplied by log2(e)/sqrt(64); Vt bf16
+ * and O bf16 in the layouts above; segs as for mf_op_attention.  S = q k^T is computed on E4M3 MFMA
+ * with the row scales in the MFMA's scale operands; the softmax and P V are those of the bf16 path.
+ * dim = 64 heads, mpad % 8 == 0; MF_EINVAL otherwise. */
+mf_status mf_op_attention_fp8(int32_t heads, int32_t dim, const void* q8, const void* qe, const void* k8,
+                              const void* ke, const void* vt, void* o, int64_t mpad, const int32_t* segs,
+                              int32_t nseg, void* stream);
 
 /* C[M][N] = A[M][K] Bt[N][K]^T + bias (fp32 out; bias nullable).  A, Bt in the precision's
  * type, device memory; N a multiple of 128; K a multiple of 64 (bf16) / 32 (fp32). */

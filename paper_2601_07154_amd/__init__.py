@@ -289,3 +289,13 @@ def op_quantize_fp8_windows_noalloc(y, segs, q, srow, stream: int = 0):
     _check(lib.mf_op_quantize_fp8_windows_noalloc(_ptr(y)[0], y.shape[1], C.c_void_p(s.ctypes.data), s.shape[0],
                                                   _ptr(q)[0], _ptr(srow)[0], C.c_void_p(stream)),
            "mf_op_quantize_fp8_windows_noalloc")
+
+
+def op_attention_fp8(heads: int, dim: int, q8, qe, k8, ke, vt, o, mpad: int, segs, stream: int = 0):
+    """Attention with E4M3 scores: q8/k8 uint8 [heads][mpad][64], qe/ke uint8 [heads][mpad] (E8M0 exponents),
+    vt bfloat16 [heads][64][mpad], o bfloat16 [rows][dim] (device tensors); segs [nseg][4]."""
+    s = np.ascontiguousarray(segs, dtype=np.int32).reshape(-1, 4)
+    lib = _lib.lib()
+    _check(lib.mf_op_attention_fp8(heads, dim, _ptr(q8)[0], _ptr(qe)[0], _ptr(k8)[0], _ptr(ke)[0], _ptr(vt)[0],
+                                   _ptr(o)[0], mpad, C.c_void_p(s.ctypes.data), s.shape[0], C.c_void_p(stream)),
+           "mf_op_attention_fp8")

@@ -538,6 +538,219 @@ __global__ __launch_bounds__(256, 2) void attn_kernel_v3(const bf16* __restrict_
 }
 }  // namespace v3
 
+// attn_kernel_f8qk: attn_kernel_v3 with the scores on E4M3 operands.  Queries and keys arrive as
+// E4M3 rows with one E8M0 scale per row (per token and head); S^T = K Q^T is one
+// v_mfma_scale_f32_32x32x64_f8f6f4 per 32 keys and query block, the per-row scales riding in the
+// MFMA's scale operands (lane (row, k-half) supplies its row's exponent), so the product is already
+// in base-2 exponent units and accumulates onto -m as in v3.  K tiles are 64 bytes per key in LDS
+// (chunks XOR-swizzled by (row >> 2) & 3), with their scale bytes beside them; the softmax, the
+// bf16 probabilities and O^T += V^T P^T are v3's.
+namespace f8qk {
+using v3::HD; using v3::KT; using v3::KS; using v3::QW; using v3::QT; using v3::VCPR; using v3::GROW;
+using v3::fast_exp2; using v3::pair_max; using v3::pair_sum; using v3::probs;
+constexpr int K8CPR = 4;   // 16-byte chunks per E4M3 K row (64 d)
+
+__global__ __launch_bounds__(256, 2) void attn_kernel_f8qk(const unsigned char* __restrict__ Q8,
+                                                           const unsigned char* __restrict__ Qe,
+                                                           const unsigned char* __restrict__ K8,
+                                                           const unsigned char* __restrict__ Ke,
+                                                           const bf16* __restrict__ Vt, bf16* __restrict__ O,
+                                                           int64_t mpad, int heads, int dim,
+                                                           const AttnSeg* __restrict__ segs,
+                                                           const AttnWork* __restrict__ work, int nwork) {
+  __shared__ u32x4 sK[2][KT * K8CPR];
+  __shared__ unsigned sKe[2][KT / 4];
+  __shared__ u32x4 sV[2][HD * VCPR];
+  const int nb = nwork * heads;
+  const int bid = xcd_remap(blockIdx.x, nb);
+  const int h = bid / nwork, wi = bid - h * nwork;
+  const AttnWork wk = work[wi];
+  const AttnSeg sg = segs[wk.seg];
+  const int seg_len = sg.nf * sg.npad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 5, l32 = lane & 31;
+  const int qbase = wk.q0 + wave * QW;
+
+  const int64_t hrow = (int64_t)h * mpad + sg.base;   // row of the segment's first token in [H][mpad]
+  const unsigned char* Qh = Q8 + hrow * HD;
+  const unsigned char* Kh = K8 + hrow * HD;
+  const unsigned char* Keh = Ke + hrow;
+  const bf16* Vh = Vt + (int64_t)h * HD * mpad + sg.base;
+
+  // query block hb: lane (query l32, k-half g) holds bytes 32 g .. 32 g + 31 of its row
+  i32x8 qf[2];
+  int qsc[2];
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb) {
+    const int row = qbase + hb * 32 + l32;
+    const u32x4* qr = (const u32x4*)(Qh + (int64_t)row * HD);
+    const u32x4 c0 = qr[2 * g], c1 = qr[2 * g + 1];
+    qf[hb] = (i32x8){(int)c0.x, (int)c0.y, (int)c0.z, (int)c0.w, (int)c1.x, (int)c1.y, (int)c1.z, (int)c1.w};
+    qsc[hb] = (int)Qe[hrow + row];
+  }
+
+  // K tile: thread -> row tid/2, chunks 2 (tid%2) .. +1; scale bytes: threads 0..31, 4 rows each.
+  // V^T tile as in v3.  The next tile goes through registers (K first, then V).
+  u32x4 rk[2];
+  unsigned rks = 0u;
+  u32x4 rv[4];
+  auto load_k = [&](int kt) {
+    const u32x4* ksrc = (const u32x4*)(Kh + (int64_t)(kt + (tid >> 1)) * HD) + 2 * (tid & 1);
+    rk[0] = ksrc[0];
+    rk[1] = ksrc[1];
+    if (tid < KT / 4) rks = *(const unsigned*)(Keh + kt + 4 * tid);
+  };
+  auto load_v = [&](int kt) {
+    const u32x4* vsrc = (const u32x4*)(Vh + (int64_t)(tid >> 2) * mpad + kt + (tid & 3) * 32);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rv[i] = vsrc[i];
+  };
+  auto store_k = [&](int buf) {
+    const int krow = tid >> 1, ksw = (krow >> 2) & 3;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) sK[buf][krow * K8CPR + ((2 * (tid & 1) + i) ^ ksw)] = rk[i];
+    if (tid < KT / 4) sKe[buf][tid] = rks;
+  };
+  auto store_v = [&](int buf) {
+    const int vrow = tid >> 2, sw = vrow & 15;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int ch = 4 * (tid & 3) + 2 * p;
+      const u32x4 lo = {rv[2 * p].x, rv[2 * p].y, rv[2 * p + 1].x, rv[2 * p + 1].y};
+      const u32x4 hi = {rv[2 * p].z, rv[2 * p].w, rv[2 * p + 1].z, rv[2 * p + 1].w};
+      sV[buf][vrow * VCPR + (ch ^ sw)] = lo;
+      sV[buf][vrow * VCPR + ((ch + 1) ^ sw)] = hi;
+    }
+  };
+
+  f32x16 o[2][2];
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) o[hb][t][r] = 0.0f;
+  float l_run[2] = {0.0f, 0.0f};
+  float m_cur[2] = {0.0f, 0.0f};
+  f32x16 mneg[2];
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) mneg[hb][r] = 0.0f;
+
+  const int key_end = sg.nf == 1 ? sg.n : seg_len;
+  const int nsteps = (key_end + KS - 1) / KS;
+  const int ntiles = (nsteps + 3) / 4;
+
+  auto step = [&](int cur, int sub, int st) {
+    const int k0 = st * KS;
+    const int krow = sub * KS + l32, ksw = (krow >> 2) & 3;
+    const u32x4 c0 = sK[cur][krow * K8CPR + ((2 * g) ^ ksw)];
+    const u32x4 c1 = sK[cur][krow * K8CPR + ((2 * g + 1) ^ ksw)];
+    const i32x8 kf = {(int)c0.x, (int)c0.y, (int)c0.z, (int)c0.w, (int)c1.x, (int)c1.y, (int)c1.z, (int)c1.w};
+    const int ksc = (int)((sKe[cur][krow >> 2] >> (8 * (krow & 3))) & 255u);
+    f32x16 s[2];
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb)
+      s[hb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(kf, qf[hb], mneg[hb], 0, 0, 0, ksc, 0, qsc[hb]);
+    const int f0 = k0 / sg.npad;
+    const bool full = k0 + KS <= (f0 * sg.npad + sg.n) && k0 + KS <= key_end;
+    if (!full) {
+      const unsigned bits = key_mask(k0, g, key_end, sg.npad, sg.n);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const bool ok = (bits >> r) & 1u;
+        s[0][r] = ok ? s[0][r] : -INFINITY;
+        s[1][r] = ok ? s[1][r] : -INFINITY;
+      }
+    }
+    u32x4 vf[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int drow = t * 32 + l32;
+#pragma unroll
+      for (int j2 = 0; j2 < 2; ++j2) vf[t][j2] = sV[cur][drow * VCPR + ((4 * sub + 2 * j2 + g) ^ (drow & 15))];
+    }
+#pragma unroll
+    for (int hb = 0; hb < 2; ++hb) {
+      u32x4 pf[2];
+      float ls;
+      probs(s[hb], 0.0f, pf, ls, false);
+      if (__any(st == 0 || !(ls <= GROW))) {
+        float mx = s[hb][0];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) mx = fmaxf(mx, s[hb][r]);
+        const float m_old = m_cur[hb];
+        mx = pair_max(mx) + m_old;
+        float m_new = st == 0 ? mx : fmaxf(m_old, mx);
+        m_new = m_new > -INFINITY ? m_new : 0.0f;
+        const float alpha = st == 0 ? 1.0f : fast_exp2(m_old - m_new);
+        m_cur[hb] = m_new;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mneg[hb][r] = -m_new;
+        l_run[hb] *= alpha;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) o[hb][t][r] *= alpha;
+        probs(s[hb], m_new - m_old, pf, ls, true);
+      }
+      l_run[hb] += ls;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j2 = 0; j2 < 2; ++j2)
+          o[hb][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)&vf[t][j2], *(const bf16x8*)&pf[j2],
+                                                             o[hb][t], 0, 0, 0);
+    }
+  };
+
+  load_k(0);
+  store_k(0);
+  load_v(0);
+  store_v(0);
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb) asm volatile("" : : "v"(qf[hb]), "v"(qsc[hb]));
+  __syncthreads();
+  for (int tile = 0; tile < ntiles; ++tile) {
+    const int cur = tile & 1, st0 = tile * 4;
+    const bool more = tile + 1 < ntiles;
+    const int kt_next = (tile + 1) * KT;
+    if (more) load_k(kt_next);
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub) {
+      if (st0 + sub < nsteps) step(cur, sub, st0 + sub);
+      if (sub == 1 && more) {
+        store_k(cur ^ 1);
+        load_v(kt_next);
+      }
+    }
+    if (more) {
+      store_v(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb) {
+    const int qrow = qbase + hb * 32 + l32;
+    const float inv = 1.0f / pair_sum(l_run[hb]);
+    if (qrow < seg_len) {
+      bf16* orow = O + (int64_t)(sg.base + qrow) * dim + h * HD;
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bf16x4 v;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[i] = (bf16)(o[hb][t][4 * j + i] * inv);
+          *(bf16x4*)(orow + t * 32 + 8 * j + 4 * g) = v;
+        }
+    }
+  }
+}
+}  // namespace f8qk
+
 template <typename T, int HD>
 static hipError_t launch(const void* q, const void* k, const void* vt, void* o, int64_t mpad,
                          int heads, int dim, const AttnSeg* segs, const AttnWork* work, int nwork,
@@ -551,6 +764,16 @@ static hipError_t launch(const void* q, const void* k, const void* vt, void* o, 
 int attention_q_tile(Dtype dt, int hd) { return (dt == DT_BF16 && hd == 64) ? v3::QT : 128; }
 
 float attention_q_scale(int hd) { return (float)(1.4426950408889634 / sqrt((double)hd)); }
+
+hipError_t attention_fp8qk(const unsigned char* q8, const unsigned char* qe8, const unsigned char* k8,
+                           const unsigned char* ke8, const void* vt, void* o, int64_t mpad, int heads, int dim,
+                           const AttnSeg* segs, const AttnWork* work, int nwork, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  if (dim != heads * 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(f8qk::attn_kernel_f8qk, dim3(nwork * heads), dim3(256), 0, s, q8, qe8, k8, ke8, (const bf16*)vt,
+                     (bf16*)o, mpad, heads, dim, segs, work, nwork);
+  return hipGetLastError();
+}
 
 hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void* vt, void* o,
                      int64_t mpad, int heads, int dim, const AttnSeg* segs, const AttnWork* work,

@@ -63,3 +63,26 @@ MF_DEV float erf_as7126(float x) {
   return copysignf(fmaf(-poly, e, 1.0f), x);
 }
 MF_DEV float gelu_erf_fast(float z) { return 0.5f * z * (1.0f + erf_as7126(z * 0.70710678118654752f)); }
+
+// fp32 -> OCP E4M3 with round-to-nearest-even, saturating at +-448 (the scale maps the amax to 448).
+MF_DEV unsigned pack4_fp8(float a, float b, float c, float d) {
+  a = fminf(fmaxf(a, -448.0f), 448.0f);
+  b = fminf(fmaxf(b, -448.0f), 448.0f);
+  c = fminf(fmaxf(c, -448.0f), 448.0f);
+  d = fminf(fmaxf(d, -448.0f), 448.0f);
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  return (unsigned)w;
+}
+
+// The least integer e with 448 * 2^e >= amax, from the bits of amax = m 2^E (m in [1, 2)):
+// amax / 448 = (m / 1.75) 2^(E - 8) and m / 1.75 lies in (0.5, 1] for m <= 1.75, so e = E - 8 there and
+// E - 7 above (mantissa field beyond 0x600000).  0 for amax = 0; normal amax only (the E4M3 operands
+// this scales have amax >= 2^-126 or are zero rows).
+MF_DEV int e4m3_row_exponent(float amax) {
+  const unsigned u = __float_as_uint(amax);
+  if (!(amax > 0.0f)) return 0;
+  const int E = (int)((u >> 23) & 255u) - 127;
+  const int e = E - 8 + ((u & 0x7fffffu) > 0x600000u ? 1 : 0);
+  return e < -127 ? -127 : (e > 126 ? 126 : e);   // the E8M0 range with 2^-e a normal fp32
+}

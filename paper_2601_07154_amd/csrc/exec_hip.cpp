@@ -71,6 +71,7 @@ class HipExecutor : public Executor {
     dt_ = m.precision == MF_FP32 ? DT_F32 : DT_BF16;
     es_ = dt_ == DT_BF16 ? 2 : 4;
     qt_ = attention_q_tile(dt_, hd_);
+    fp8_attn_ = fp8_ && hd_ == 64;   // MF_FP8 scores on E4M3 operands (head dim 64)
     const size_t want = expected_floats();
     if (n != want) { err = "weight blob has " + std::to_string(n) + " floats, the model needs " + std::to_string(want); return MF_EINVAL; }
     if (!rt.dev_alloc != !rt.dev_free) { err = "dev_alloc and dev_free go together"; return MF_EINVAL; }
@@ -448,12 +449,13 @@ class HipExecutor : public Executor {
 
   mf_status debug_copy(int which, void* host, size_t bytes, std::string& err) override {
     HIPCHECK(hipSetDevice(device_));
-    const void* src[7] = {X_, Y_, Q_, K_, Vt_, O_, Hb_};
+    const void* src[11] = {X_, Y_, Q_, K_, Vt_, O_, Hb_, Q8_, K8_, QE_, KE_};
     const size_t D = D_, wide = std::max<int64_t>(F_, KP);
-    const size_t cap[7] = {(size_t)mcap_ * D * 4, (size_t)mcap_ * D * es_, (size_t)mpad_ * D * es_,
+    const size_t q8b = fp8_attn_ ? (size_t)mpad_ * D : 0, qeb = fp8_attn_ ? (size_t)mpad_ * H_ : 0;
+    const size_t cap[11] = {(size_t)mcap_ * D * 4, (size_t)mcap_ * D * es_, (size_t)mpad_ * D * es_,
                            (size_t)mpad_ * D * es_, (size_t)mpad_ * D * es_, (size_t)mcap_ * D * es_,
-                           (size_t)mcap_ * wide * es_};
-    if (which < 0 || which > 6 || bytes > cap[which]) { err = "bad buffer or size"; return MF_EINVAL; }
+                           (size_t)mcap_ * wide * es_, q8b, q8b, qeb, qeb};
+    if (which < 0 || which > 10 || bytes > cap[which] || !src[which]) { err = "bad buffer or size"; return MF_EINVAL; }
     HIPCHECK(hipStreamSynchronize(st_));
     HIPCHECK(hipMemcpy(host, src[which], bytes, hipMemcpyDeviceToHost));
     return MF_OK;
@@ -498,7 +500,8 @@ class HipExecutor : public Executor {
   }
   uint64_t workspace_bytes() const {
     const uint64_t D = D_, wide = std::max<int64_t>(F_, KP);
-    const uint64_t f8 = fp8_ ? (uint64_t)mcap_ * (D + F_ + 8) : 0;
+    const uint64_t f8 = (fp8_ ? (uint64_t)mcap_ * (D + F_ + 8) : 0) +
+                        (fp8_attn_ ? (uint64_t)mpad_ * 2 * (D + (uint64_t)H_) : 0);
     return f8 + (uint64_t)mcap_ * (D * 4 + D * es_ + D * es_ + wide * es_ + 4 + 4) + (uint64_t)mpad_ * 3 * D * es_ +
            (uint64_t)fcap_ * (2 * D * 4 + 9 * 4 + 16 * 8 + sizeof(mf_focus) * 2 + 8 + 8) + (64u << 20);
   }
@@ -595,6 +598,18 @@ class HipExecutor : public Executor {
     HIPCHECK(hipStreamSynchronize(st_));
     if (fp8_) {
       HIPCHECK(dmalloc(&Y8_, (size_t)mcap_ * D));
+      if (fp8_attn_) {
+        // E4M3 q / k rows and their per-row scale bytes; rows past the tokens stay zero (finite)
+        HIPCHECK(dmalloc(&Q8_, (size_t)mpad_ * D_));
+        HIPCHECK(dmalloc(&K8_, (size_t)mpad_ * D_));
+        HIPCHECK(dmalloc(&QE_, (size_t)mpad_ * H_));
+        HIPCHECK(dmalloc(&KE_, (size_t)mpad_ * H_));
+        HIPCHECK(hipMemsetAsync(Q8_, 0, (size_t)mpad_ * D_, st_));
+        HIPCHECK(hipMemsetAsync(K8_, 0, (size_t)mpad_ * D_, st_));
+        HIPCHECK(hipMemsetAsync(QE_, 0, (size_t)mpad_ * H_, st_));
+        HIPCHECK(hipMemsetAsync(KE_, 0, (size_t)mpad_ * H_, st_));
+        HIPCHECK(hipStreamSynchronize(st_));
+      }
       HIPCHECK(dmalloc(&H8_, (size_t)mcap_ * F_));
       HIPCHECK(dmalloc(&srow_, (size_t)mcap_ * 4));
       HIPCHECK(dmalloc(&srow2_, (size_t)mcap_ * 4));
@@ -726,6 +741,7 @@ class HipExecutor : public Executor {
       q.A = Y_; q.lda = D; q.Bt = L.Wqkv; q.ldb = D; q.M = M; q.N = 3 * D; q.K = D; q.bias = L.b_qkv;
       q.q = Q_; q.k = K_; q.vt = Vt_; q.heads = H_; q.hd = hd_; q.mpad = mpad_;
       q.qscale = attention_q_scale(hd_);
+      if (fp8_attn_) { q.q8 = Q8_; q.k8 = K8_; q.qe8 = QE_; q.ke8 = KE_; }
       if (fp8_) {
         HIPCHECK(quant(Y_, D, Y8_, srow_));
         q.A = Y8_;
@@ -735,10 +751,13 @@ class HipExecutor : public Executor {
       HIPCHECK(run_gemm(EPI_QKV, q, MF_STAGE_QKV, fp8_));
       const bool global = (l % 2) == 1;
       prof_begin();
-      if (global)
-        HIPCHECK(attention(dt_, hd_, Q_, K_, Vt_, O_, mpad_, H_, D, gsegs, gwork, (int)p.gwork.size(), st_));
+      const AttnSeg* segs = global ? gsegs : fsegs;
+      const AttnWork* wl = global ? gwork : fwork;
+      const int nw = (int)(global ? p.gwork.size() : p.fwork.size());
+      if (fp8_attn_)
+        HIPCHECK(attention_fp8qk(Q8_, QE_, K8_, KE_, Vt_, O_, mpad_, H_, D, segs, wl, nw, st_));
       else
-        HIPCHECK(attention(dt_, hd_, Q_, K_, Vt_, O_, mpad_, H_, D, fsegs, fwork, (int)p.fwork.size(), st_));
+        HIPCHECK(attention(dt_, hd_, Q_, K_, Vt_, O_, mpad_, H_, D, segs, wl, nw, st_));
       prof_end(global ? MF_STAGE_ATTN_GLOBAL : MF_STAGE_ATTN_FRAME);
       GemmArgs o{};
       o.A = O_; o.lda = D; o.Bt = L.Wo; o.ldb = D; o.M = M; o.N = D; o.K = D; o.bias = L.b_o; o.C = X_; o.ldc = D;
@@ -850,7 +869,7 @@ class HipExecutor : public Executor {
     for (auto& L : layers_) { F(L.Wqkv); F(L.Wo); F(L.W1); F(L.W2); }
     F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(rowframe_); F(win_scale_); F(Q_); F(K_); F(Vt_);
     F(Wd_); F(bd_);
-    F(Y8_); F(H8_); F(srow_); F(srow2_); F(amax_); F(wscale_); F(wamax_);
+    F(Y8_); F(H8_); F(srow_); F(srow2_); F(amax_); F(wscale_); F(wamax_); F(Q8_); F(K8_); F(QE_); F(KE_);
     F(camln_); F(camg_); F(pose9_); F(tloc_); F(res_); F(keys_); F(psum_); F(pe_); F(tab_dev_);
     if (res_host_) hipHostFree(res_host_);
     if (tab_host_) hipHostFree(tab_host_);
@@ -928,6 +947,8 @@ class HipExecutor : public Executor {
   bool use_graphs_ = false;
   bool fp8_ = false;
   unsigned char *Y8_ = nullptr, *H8_ = nullptr;
+  bool fp8_attn_ = false;
+  unsigned char *Q8_ = nullptr, *K8_ = nullptr, *QE_ = nullptr, *KE_ = nullptr;
   float *srow_ = nullptr, *srow2_ = nullptr, *wscale_ = nullptr;
   unsigned *amax_ = nullptr, *wamax_ = nullptr;
   struct GraphEntry {

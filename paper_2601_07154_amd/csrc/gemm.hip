@@ -163,6 +163,28 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
       for (int p = 0; p < 8; ++p) {
         const int r = rr + 4 * p;
         const int m = m0 + wr * 32 * WM + i * 32 + r;
+        if constexpr (EPI == EPI_QKV) {
+          // E4M3 copy of a q / k row for the fp8 attention scores: the 16 lanes of this row hold its
+          // 64 columns (one head), so the row's amax is a reduction over those 16 lanes (run by every
+          // lane: inactive rows contribute 0)
+          if (a.q8 && which < 2) {
+            const bool ok = m < a.M;
+            f32x4 v = *(const f32x4*)(stage + r * SR + c4);
+            const float sc = (ok && a.ascale) ? a.ascale[m] * bs : 1.0f;
+            v = (v * sc + bias4) * qs;
+            float mx = ok ? fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))) : 0.0f;
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+            const int e = e4m3_row_exponent(mx);
+            const float inv = __uint_as_float((unsigned)(127 - e) << 23);   // 2^-e, exact
+            const unsigned pk = pack4_fp8(v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv);
+            if (ok) {
+              const int64_t hrow = qoff / a.hd;   // h * mpad (qoff = h mpad hd + d, d < hd)
+              *(unsigned*)((which == 0 ? a.q8 : a.k8) + qoff + (int64_t)m * a.hd) = pk;
+              if ((lane & 15) == 0) (which == 0 ? a.qe8 : a.ke8)[hrow + m] = (unsigned char)(e + 127);
+            }
+          }
+        }
         if (m < a.M) {
           f32x4 v = *(const f32x4*)(stage + r * SR + c4);
           const float sc = a.ascale ? a.ascale[m] * bs : 1.0f;

@@ -35,6 +35,10 @@ struct GemmArgs {
   // scale factors; C = depth maps: dst[(14 py + n / 14) W + 14 px + n % 14] = scale exp(acc + bias)
   // for output columns n < 196 of a patch row (py, px)
   const int32_t* rowframe; const DepthFrame* dframes; const double* win_scale;
+  // EPI_QKV, head dim 64, when q8 is set: the q and k blocks are also written as OCP E4M3 rows
+  // [H][mpad][64] scaled per token and head by 2^-e (e the least integer with 448 2^e >= the row's
+  // amax), with the E8M0 byte e + 127 in qe8 / ke8 [H][mpad]
+  unsigned char *q8, *k8, *qe8, *ke8;
 };
 hipError_t gemm(Dtype dt, Epi epi, const GemmArgs& a, hipStream_t s);
 
@@ -51,6 +55,12 @@ hipError_t scale_copy(Dtype dt, const void* x, void* y, int64_t n, float s, hipS
 hipError_t attention(Dtype dt, int hd, const void* q, const void* k, const void* vt, void* o,
                      int64_t mpad, int heads, int dim, const AttnSeg* segs, const AttnWork* work,
                      int nwork, hipStream_t s);
+// The same with the scores on E4M3 operands (head dim 64): q8 / k8 [H][mpad][64] E4M3 rows with
+// E8M0 per-row scale bytes qe8 / ke8 [H][mpad] (queries pre-multiplied by attention_q_scale), V^T and
+// O bf16; the work list is attention_q_tile(DT_BF16, 64) queries per item.
+hipError_t attention_fp8qk(const unsigned char* q8, const unsigned char* qe8, const unsigned char* k8,
+                           const unsigned char* ke8, const void* vt, void* o, int64_t mpad, int heads, int dim,
+                           const AttnSeg* segs, const AttnWork* work, int nwork, hipStream_t s);
 
 // ---------------------------------------------------------------- LayerNorm (fp32 in, dtype out)
 // rows: optional gather table (out row i <- in row rows[i]).

@@ -204,17 +204,6 @@ hipError_t pose_out(const float* g, const float* H2, const float* h2, int F, int
 // ------------------------------------------------------------------ FP8 (OCP E4M3) quantisation
 namespace mf {
 
-// fp32 -> E4M3 with round-to-nearest-even, saturating at +-448 (the scale maps the amax to 448).
-MF_DEV unsigned pack4_fp8(float a, float b, float c, float d) {
-  a = fminf(fmaxf(a, -448.0f), 448.0f);
-  b = fminf(fmaxf(b, -448.0f), 448.0f);
-  c = fminf(fmaxf(c, -448.0f), 448.0f);
-  d = fminf(fmaxf(d, -448.0f), 448.0f);
-  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
-  return (unsigned)w;
-}
-
 __global__ void fill_u32_kernel(unsigned* p, int n, unsigned v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

@@ -55,6 +55,38 @@ mf_status mf_op_attention(int32_t precision, int32_t head_dim, int32_t heads, in
   return r == hipSuccess ? MF_OK : MF_EDEVICE;
 }
 
+mf_status mf_op_attention_fp8(int32_t heads, int32_t dim, const void* q8, const void* qe, const void* k8,
+                              const void* ke, const void* vt, void* o, int64_t mpad, const int32_t* segs, int32_t nseg,
+                              void* stream) {
+  if (!q8 || !qe || !k8 || !ke || !vt || !o || !segs || nseg < 1 || heads < 1 || dim != heads * 64) return MF_EINVAL;
+  std::vector<AttnSeg> sg(nseg);
+  std::vector<AttnWork> wk;
+  const int qt = attention_q_tile(DT_BF16, 64);
+  for (int i = 0; i < nseg; ++i) {
+    sg[i] = {segs[4 * i], segs[4 * i + 1], segs[4 * i + 2], segs[4 * i + 3]};
+    const AttnSeg& s = sg[i];
+    if (s.base < 0 || s.nf < 1 || s.n < 1 || s.npad < s.n || s.npad % 8 || s.base % 8) return MF_EINVAL;
+    if ((int64_t)s.base + (int64_t)s.nf * s.npad + 256 > mpad) return MF_EINVAL;
+    const int qend = s.nf == 1 ? s.n : s.nf * s.npad;
+    for (int q0 = 0; q0 < qend; q0 += qt) wk.push_back({i, q0});
+  }
+  if (mpad % 8) return MF_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  void* dev = nullptr;
+  const size_t sb = sg.size() * sizeof(AttnSeg), wb = wk.size() * sizeof(AttnWork);
+  if (hipMalloc(&dev, sb + wb) != hipSuccess) return MF_EDEVICE;
+  hipError_t r = hipMemcpyAsync(dev, sg.data(), sb, hipMemcpyHostToDevice, st);
+  if (r == hipSuccess) r = hipMemcpyAsync((char*)dev + sb, wk.data(), wb, hipMemcpyHostToDevice, st);
+  if (r == hipSuccess)
+    r = attention_fp8qk((const unsigned char*)q8, (const unsigned char*)qe, (const unsigned char*)k8,
+                        (const unsigned char*)ke, vt, o, mpad, heads, dim, (const AttnSeg*)dev,
+                        (const AttnWork*)((char*)dev + sb), (int)wk.size(), st);
+  const hipError_t rs = hipStreamSynchronize(st);
+  if (r == hipSuccess) r = rs;
+  hipFree(dev);
+  return r == hipSuccess ? MF_OK : MF_EDEVICE;
+}
+
 mf_status mf_op_gemm(int32_t precision, const void* A, const void* Bt, const float* bias, float* C, int32_t M,
                      int32_t N, int32_t K, void* stream) {
   if (!A || !Bt || !C || M < 0 || N % 128 || K <= 0) return MF_EINVAL;

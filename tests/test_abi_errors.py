@@ -131,3 +131,14 @@ def test_engine_create_checks_the_depth_head_blob(lib, flag, extra):
     st = lib.mf_engine_create(C.byref(m), C.c_void_p(blob.ctypes.data), blob.size, C.byref(rt), C.byref(h))
     assert st == _lib.MF_EINVAL and not h.value
     assert "floats" in lib.mf_last_error().decode()
+
+
+@pytest.mark.parametrize("heads,dim,segs,mpad", [(2, 100, [[0, 1, 10, 16]], 1024),   # dim != 64 heads
+                                                 (2, 128, [[0, 1, 10, 12]], 1024),   # npad not a multiple of 8
+                                                 (2, 128, [[0, 60, 10, 16]], 1024),  # past mpad - 256
+                                                 (2, 128, [[0, 1, 10, 16]], 1020)])  # mpad not a multiple of 8
+def test_op_attention_fp8_rejects(lib, heads, dim, segs, mpad):
+    from paper_2601_07154_amd import _lib
+    arr, p, n = _segs(segs)
+    st = lib.mf_op_attention_fp8(heads, dim, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, mpad, p, n, None)
+    assert st == _lib.MF_EINVAL

@@ -1,6 +1,8 @@
 """FP8 (OCP E4M3) path: the quantiser against the oracle's E4M3 rounding, the E4M3 MFMA GEMM on
 exactly representable inputs, and the fp8 engine (QKV / fc1 / fc2 on E4M3 operands with per-tensor
 weight scales and per-window activation scales) against the oracle's fp8 emulation and FP64."""
+import math
+
 import numpy as np
 import pytest
 
@@ -225,3 +227,88 @@ def test_fp8_tiny_poses_within_emulated_error():
     R = T[:, :3, :3]
     np.testing.assert_allclose(R @ R.transpose(0, 2, 1), np.tile(np.eye(3), (wl.frames, 1, 1)), atol=1e-12)
 
+
+
+def _fp8_attention_case(torch, frames, n, heads=2, seed=41):
+    """E4M3 query and key rows with per-row power-of-two scales (the oracle's row quantiser applied
+    to queries already multiplied by log2(e)/sqrt(64) in fp32), bf16 V, in the library layouts."""
+    rng = np.random.default_rng(seed)
+    hd = 64
+    npad = (n + 7) // 8 * 8
+    mpad = frames * npad + 256 + 64
+    c = np.float32(math.log2(math.e) / math.sqrt(hd))
+    q = (rng.normal(0, 1.5, (heads, mpad, hd)).astype(np.float32) * c).astype(np.float64)
+    k = rng.normal(0, 1.5, (heads, mpad, hd)).astype(np.float32).astype(np.float64)
+    v = vit.round_bf16(rng.normal(0, 1, (heads, mpad, hd)))
+    q8, eq = vit.quantise_rows_e4m3(q)
+    k8, ek = vit.quantise_rows_e4m3(k)
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt).contiguous()
+    d = dict(q8=dev(e4m3_encode(q8), torch.uint8), k8=dev(e4m3_encode(k8), torch.uint8),
+             qe=dev((eq + 127).astype(np.uint8), torch.uint8), ke=dev((ek + 127).astype(np.uint8), torch.uint8),
+             vt=dev(v.transpose(0, 2, 1).astype(np.float32), torch.bfloat16))
+    qd, kd = q8 * 2.0 ** eq[..., None], k8 * 2.0 ** ek[..., None]     # the decoded operands
+    return d, qd, kd, v, npad, mpad
+
+
+def _softmax2_attention(qd, kd, v):
+    s = qd @ kd.T                                 # base-2 exponent units
+    p = np.exp2(s - s.max(axis=1, keepdims=True))
+    return (p @ v) / p.sum(axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("n,frames", [(145, 3), (300, 2), (65, 4)])
+def test_attention_fp8_scores_match_fp64_on_decoded_operands(n, frames):
+    """The attention with E4M3 scores (MF_FP8, head dim 64) against FP64 on the decoded E4M3 operands:
+    the scores are exact products of representable values accumulated in fp32, so only the bf16
+    rounding of the probabilities separates the two (the bf16 attention test's 1.5e-2); frame-wise
+    segments and one global segment with the padding keys masked."""
+    torch = torch_cuda()
+    m = mf()
+    heads, D = 2, 128
+    d, qd, kd, v, npad, mpad = _fp8_attention_case(torch, frames, n, heads)
+    o = torch.zeros((mpad, D), device="cuda", dtype=torch.bfloat16)
+    m.op_attention_fp8(heads, D, d["q8"], d["qe"], d["k8"], d["ke"], d["vt"], o, mpad,
+                       [[f * npad, 1, n, npad] for f in range(frames)])
+    got = o.float().cpu().numpy()
+    for f in range(frames):
+        r = slice(f * npad, f * npad + n)
+        for h in range(heads):
+            ref = _softmax2_attention(qd[h, r], kd[h, r], v[h, r])
+            np.testing.assert_allclose(got[r, h * 64:(h + 1) * 64], ref, atol=1.5e-2, rtol=1.5e-2)
+    o.zero_()
+    m.op_attention_fp8(heads, D, d["q8"], d["qe"], d["k8"], d["ke"], d["vt"], o, mpad, [[0, frames, n, npad]])
+    got = o.float().cpu().numpy()
+    valid = np.concatenate([np.arange(f * npad, f * npad + n) for f in range(frames)])
+    for h in range(heads):
+        ref = _softmax2_attention(qd[h, valid], kd[h, valid], v[h, valid])
+        np.testing.assert_allclose(got[valid, h * 64:(h + 1) * 64], ref, atol=1.5e-2, rtol=1.5e-2)
+
+
+def test_qkv_epilogue_writes_e4m3_rows_with_least_power_of_two_scales():
+    """In an fp8 engine the QKV projection also writes every query and key row of every head as E4M3
+    with an E8M0 exponent: decoded, it matches the bf16 rows of the same projection within an E4M3
+    rounding (plus the bf16 rounding), and each non-zero row reaches the top binade (|code| max in
+    [224, 448]), which makes its exponent the least that fits."""
+    torch = torch_cuda()
+    m = mf()
+    S, H, W = 3, 56, 84
+    blob = mf_synth.make_weights(MODEL, 2, std=0.05)
+    frames = mf_synth.make_frames(S, H, W, 6)
+    eng = m.Engine.from_model(MODEL, blob, precision="fp8", max_tokens=2048)
+    eng.forward_window(torch.from_numpy(frames).cuda(), max_layers=1)
+    hd, heads = 64, MODEL.heads
+    mpad = (2048 + 7) // 8 * 8 + 256
+    bf = lambda u: (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    n = (H // 14) * (W // 14) + 1
+    npad = m.rows_per_frame(H, W)
+    rows = np.concatenate([np.arange(f * npad, f * npad + n) for f in range(S)])
+    for which, w8, we in ((2, 7, 9), (3, 8, 10)):
+        ref = bf(eng.debug_copy(which, (heads, mpad, hd), np.uint16))[:, rows]
+        codes = eng.debug_copy(w8, (heads, mpad, hd), np.uint8)[:, rows]
+        e = eng.debug_copy(we, (heads, mpad), np.uint8)[:, rows].astype(np.float64) - 127.0
+        dec = e4m3_decode(codes) * 2.0 ** e[..., None]
+        tol = 2.0 ** -4 * np.abs(ref) + 2.0 ** -8 * np.abs(ref) + 2.0 ** (e[..., None] - 9)
+        assert (np.abs(dec - ref) <= tol).all(), np.abs(dec - ref).max()
+        top = np.abs(e4m3_decode(codes)).max(axis=-1)
+        assert ((top >= 224.0) & (top <= 448.0)).all()
+    eng.close()
