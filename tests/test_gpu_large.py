@@ -1,12 +1,18 @@
-"""Step-local parity at the large workload's full size (32-frame windows of 378x504 = 31 136 tokens,
-24 layers, D=1024, 16 heads, BF16): each stage is fed the library's own previous output and checked
-against the FP64 oracle on sampled token rows (the oracle computes all keys/values, but only the
-sampled queries), so the check covers the full-size kernels without a full FP64 forward."""
+"""Parity at the large workload's full size (32-frame windows of 378x504 = 31 136 tokens, 24 layers,
+D=1024, 16 heads, BF16).
+
+End to end: the benchmark's launch configuration (the whole 256-frame stream, 15 windows in one
+fused batch) against the stored FP64 oracle outputs of windows 0-1 (tests/golden), with the BF16
+gates calibrated by the stored emulated-bf16 oracle outputs of the same windows.
+
+Step-local: each stage is fed the library's own previous output and checked against the FP64 oracle
+on sampled token rows (the oracle computes all keys/values, but only the sampled queries)."""
 import numpy as np
 import pytest
 
 import mf_synth
-from gpu_util import mf, torch_cuda
+from gpu_util import (check_emulation_gates, golden, golden_errors, mf, record_errors, run_stream_fused, summary,
+                      torch_cuda)
 from oracle import vit
 
 pytestmark = pytest.mark.gpu
@@ -89,3 +95,21 @@ def test_pose_head_full_size(setup):
     assert err < 1e-4          # the head runs in fp32 from the same tokens
     Tref = np.stack([vit.pose9_to_T(r) for r in p9.astype(np.float64)])
     np.testing.assert_allclose(T, Tref, atol=1e-12)   # quaternion -> rotation in FP64
+
+
+BF16_EMU_FACTOR = 3.0   # the gate rule of the small workload's end-to-end test
+
+
+def test_large_bf16_windows01_against_fp64():
+    torch = torch_cuda()
+    ref = golden("large_fp64_w01")
+    emu = golden_errors(golden("large_bf16emu_w01"), ref)
+    blob = mf_synth.make_weights(WL.model, WL.seed_weights)
+    frames = torch.from_numpy(mf_synth.workload_frames(WL)).cuda()
+    recs = run_stream_fused(WL, "bf16", blob, frames)
+    del frames
+    e = record_errors(recs, ref)
+    print("large bf16 vs FP64, windows 0-1: " + summary(e))
+    print("emulated bf16 vs FP64: " + summary(emu))
+    lim = check_emulation_gates(e, emu, BF16_EMU_FACTOR, pose_floor=2.0)
+    print("limits: " + ", ".join(f"{k} {v:.2f}" for k, v in lim.items()))
