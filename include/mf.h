@@ -145,6 +145,9 @@ typedef struct mf_stats {
   int32_t streams_open, streams_pending;
   uint64_t hbm_used_bytes, hbm_budget_bytes;
   double gpu_ms;            /* device time of all batches (HIP events) */
+  int64_t frames_embed_shared; /* Sec. 2.2: frames of a window whose patch embedding was taken from an
+                                  earlier window of the same stream in the same batch (the overlap
+                                  frames of consecutive windows) instead of being computed again */
 } mf_stats;
 
 /* Sec. 2.2 (the per-window pose inference of the foundation model; here the seeded ViT whose sizes

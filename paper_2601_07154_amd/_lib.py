@@ -61,7 +61,7 @@ class Stats(C.Structure):
     _fields_ = [("frames_pushed", C.c_int64), ("frames_emitted", C.c_int64), ("windows_run", C.c_int64),
                 ("batches_run", C.c_int64), ("tokens_run", C.c_int64), ("streams_open", C.c_int32),
                 ("streams_pending", C.c_int32), ("hbm_used_bytes", C.c_uint64),
-                ("hbm_budget_bytes", C.c_uint64), ("gpu_ms", C.c_double)]
+                ("hbm_budget_bytes", C.c_uint64), ("gpu_ms", C.c_double), ("frames_embed_shared", C.c_int64)]
 
 
 FOCUS_DTYPE = np.dtype({

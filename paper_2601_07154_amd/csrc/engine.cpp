@@ -286,6 +286,7 @@ static int step(Engine& e) {
   e.st.batches_run++;
   e.st.tokens_run += b.tokens;
   e.st.gpu_ms += ms;
+  e.st.frames_embed_shared += e.ex->last_batch_shared();
   e.cv.notify_all();
   return (int)b.wins.size();
 }

@@ -80,6 +80,7 @@ class Executor {
   virtual void profile(double* attn_global_ms, int64_t* attn_global_calls, double* attn_frame_ms,
                        double* gemm_ms, int enable) = 0;
   // per-stage sums (MF_STAGE_* order) of the same timing; executors without it report zeros
+  virtual int64_t last_batch_shared() const { return 0; }   // frames of the last batch that reused an embedding
   virtual void profile_stages(double* ms, int64_t* calls, int n) {
     for (int k = 0; k < n; ++k) {
       if (ms) ms[k] = 0.0;

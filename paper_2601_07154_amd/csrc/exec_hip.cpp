@@ -43,7 +43,10 @@ struct Plan {                      // host-side tables of one batch
   std::vector<AttnSeg> fsegs, gsegs;
   std::vector<AttnWork> fwork, gwork;
   std::vector<int32_t> cam_rows;
+  std::vector<int32_t> dups;       // frames whose patch embedding is copied from an earlier window
+  std::map<std::pair<int32_t, int64_t>, int32_t> seen;   // (stream, frame) -> first token row
   int64_t mtot = 0;
+  int64_t patch_rows = 0;          // rows of the patch matrix (frames embedded by the GEMM)
   int max_npad = 0;
   int max_rows = 0;                // token rows of the largest window
 };
@@ -193,7 +196,7 @@ class HipExecutor : public Executor {
       const BatchWindow& w = b.wins[i];
       if (w.poses) continue;
       loc_off[i] = fwd_frames;
-      add_window(p, w);
+      add_window(p, w, true);
       fwd_frames += w.size;
     }
     int32_t pose_rows = 0;
@@ -290,6 +293,7 @@ class HipExecutor : public Executor {
     const size_t o_jobs = reserve(jobs.size() * sizeof(MapJob));
     const size_t o_poses = reserve((size_t)pose_rows * 16 * sizeof(double));
     const size_t o_dframes = reserve(dframes.size() * sizeof(DepthFrame));
+    const size_t o_dups = reserve(p.dups.size() * sizeof(int32_t));
     mf_status rc = ensure_tables(off, err);
     if (rc != MF_OK) return rc;
     auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) memcpy(tab_host_ + o, src, bytes); };
@@ -304,6 +308,7 @@ class HipExecutor : public Executor {
     put(o_cwins, cwins.data(), cwins.size() * sizeof(ChainWin));
     put(o_jobs, jobs.data(), jobs.size() * sizeof(MapJob));
     put(o_dframes, dframes.data(), dframes.size() * sizeof(DepthFrame));
+    put(o_dups, p.dups.data(), p.dups.size() * sizeof(int32_t));
     {
       size_t po = o_poses;
       for (const BatchWindow& w : b.wins)
@@ -317,7 +322,8 @@ class HipExecutor : public Executor {
       if (!p.frames.empty()) {
         const mf_status r = forward(p, (const FrameDesc*)T(o_frames), (const AttnSeg*)T(o_fsegs),
                                     (const AttnWork*)T(o_fwork), (const AttnSeg*)T(o_gsegs),
-                                    (const AttnWork*)T(o_gwork), (const int32_t*)T(o_cam), depth_, err);
+                                    (const AttnWork*)T(o_gwork), (const int32_t*)T(o_cam),
+                                    (const int32_t*)T(o_dups), depth_, err);
         if (r != MF_OK) return r;
       }
       if (pose_rows)
@@ -346,12 +352,13 @@ class HipExecutor : public Executor {
     if (use_graphs_ && !prof_batch_) {
       // Every kernel argument and copy size follows from these counts (table offsets included):
       // the token rows, the frames and work lists, the windows and the largest of them (the fp8
-      // window quantiser's grid), the chain and map tables, the poses and the records.
+      // window quantiser's grid), the chain and map tables, the poses and the records, the patch
+      // rows and the frames that take an earlier window's embedding.
       char sig[256];
-      snprintf(sig, sizeof sig, "%lld/%d/%zu/%zu/%zu/%zu/%d/%zu/%zu/%zu/%d/%d/%d/%d/%d/%zu/%d", (long long)p.mtot,
-               p.max_npad, p.frames.size(), p.fwork.size(), p.gwork.size(), p.gsegs.size(), p.max_rows,
-               groups.size(), cwins.size(), jobs.size(), max_h, max_w, pose_rows, fwd_frames, out_n, off,
-               has_depth ? 1 : 0);
+      snprintf(sig, sizeof sig, "%lld/%d/%zu/%zu/%zu/%zu/%d/%zu/%zu/%zu/%d/%d/%d/%d/%d/%zu/%d/%lld/%zu",
+               (long long)p.mtot, p.max_npad, p.frames.size(), p.fwork.size(), p.gwork.size(), p.gsegs.size(),
+               p.max_rows, groups.size(), cwins.size(), jobs.size(), max_h, max_w, pose_rows, fwd_frames, out_n, off,
+               has_depth ? 1 : 0, (long long)p.patch_rows, p.dups.size());
       auto it = graphs_.find(sig);
       if (it == graphs_.end()) {
         if (graphs_.size() >= 64) clear_graphs();
@@ -390,6 +397,7 @@ class HipExecutor : public Executor {
     float ms = 0.0f;
     HIPCHECK(hipEventElapsedTime(&ms, ev0_, ev1_));
     if (gpu_ms) *gpu_ms = ms;
+    reused_ = (int64_t)p.dups.size();
     collect_profile(err);
     out.assign(res_host_, res_host_ + out_n);
     return MF_OK;
@@ -415,7 +423,7 @@ class HipExecutor : public Executor {
     w.start = 0;
     w.size = S;
     Plan p;
-    add_window(p, w);
+    add_window(p, w, false);
     if (p.mtot > mcap_) { err = "window exceeds the token workspace"; return MF_EINVAL; }
     size_t off = 0;
     auto reserve = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes, 256); return o; };
@@ -437,7 +445,8 @@ class HipExecutor : public Executor {
     auto T = [&](size_t o) { return (void*)(tab_dev_ + o); };
     const int layers = max_layers < 0 ? depth_ : std::min(max_layers, depth_);
     rc = forward(p, (const FrameDesc*)T(o_frames), (const AttnSeg*)T(o_fsegs), (const AttnWork*)T(o_fwork),
-                 (const AttnSeg*)T(o_gsegs), (const AttnWork*)T(o_gwork), (const int32_t*)T(o_cam), layers, err);
+                 (const AttnSeg*)T(o_gsegs), (const AttnWork*)T(o_gwork), (const int32_t*)T(o_cam), nullptr, layers,
+                 err);
     if (rc != MF_OK) return rc;
     if (pose9_host) HIPCHECK(hipMemcpyAsync(pose9_host, pose9_, (size_t)S * 9 * 4, hipMemcpyDeviceToHost, st_));
     if (T_host) HIPCHECK(hipMemcpyAsync(T_host, tloc_, (size_t)S * 16 * 8, hipMemcpyDeviceToHost, st_));
@@ -446,6 +455,8 @@ class HipExecutor : public Executor {
     collect_profile(err);
     return MF_OK;
   }
+
+  int64_t last_batch_shared() const override { return reused_; }
 
   mf_status debug_copy(int which, void* host, size_t bytes, std::string& err) override {
     HIPCHECK(hipSetDevice(device_));
@@ -584,6 +595,8 @@ class HipExecutor : public Executor {
     HIPCHECK(dmalloc(&Hb_, (size_t)mcap_ * wide * es_));
     HIPCHECK(dmalloc(&rowinfo_, (size_t)mcap_ * 4));
     HIPCHECK(dmalloc(&rowframe_, (size_t)mcap_ * 4));
+    HIPCHECK(dmalloc(&prow_, (size_t)mcap_ * 4));
+    HIPCHECK(dmalloc(&pdst_, (size_t)mcap_ * 4));
     HIPCHECK(dmalloc(&win_scale_, (size_t)fcap_ * 8));
     HIPCHECK(dmalloc(&Q_, (size_t)mpad_ * D * es_));
     HIPCHECK(dmalloc(&K_, (size_t)mpad_ * D * es_));
@@ -681,7 +694,10 @@ class HipExecutor : public Executor {
   }
 
   // ------------------------------------------------------------------ batch planning
-  void add_window(Plan& p, const BatchWindow& w) const {
+  // share: a frame that an earlier window of the batch holds too (consecutive windows of a stream
+  // share their overlap frames, Sec. 2.2) takes that window's patch embedding instead of its own
+  // im2col and GEMM rows; only the camera token (reference or not) differs.
+  void add_window(Plan& p, const BatchWindow& w, bool share) const {
     const int H = w.cfg->height, W = w.cfg->width, gw = W / 14, P = (H / 14) * gw;
     const int n = P + 1, npad = rows_per_frame(H, W);
     const size_t fb = (size_t)3 * H * W;
@@ -695,6 +711,20 @@ class HipExecutor : public Executor {
       fd.npad = npad;
       fd.first = j == 0;
       fd.pe_base = w.res->pe_base;
+      fd.patch_base = (int32_t)p.patch_rows;
+      fd.src_base = -1;
+      if (share) {
+        const auto key = std::make_pair(w.stream_id, f);
+        const auto it = p.seen.find(key);
+        if (it != p.seen.end()) {
+          fd.patch_base = -1;
+          fd.src_base = it->second;
+          p.dups.push_back((int32_t)p.frames.size());
+        } else {
+          p.seen.emplace(key, fd.token_base);
+        }
+      }
+      if (fd.patch_base >= 0) p.patch_rows += npad;
       p.frames.push_back(fd);
       p.cam_rows.push_back(fd.token_base);
       const int32_t si = (int32_t)p.fsegs.size();
@@ -711,15 +741,20 @@ class HipExecutor : public Executor {
 
   // ------------------------------------------------------------------ the network
   mf_status forward(const Plan& p, const FrameDesc* frames, const AttnSeg* fsegs, const AttnWork* fwork,
-                    const AttnSeg* gsegs, const AttnWork* gwork, const int32_t* cam_rows, int layers,
-                    std::string& err) {
+                    const AttnSeg* gsegs, const AttnWork* gwork, const int32_t* cam_rows, const int32_t* dups,
+                    int layers, std::string& err) {
     const int M = (int)p.mtot, D = D_;
-    HIPCHECK(im2col(dt_, frames, (int)p.frames.size(), p.max_npad, Hb_, KP, rowinfo_, rowframe_, st_));
+    HIPCHECK(im2col(dt_, frames, (int)p.frames.size(), p.max_npad, Hb_, KP, rowinfo_, rowframe_, prow_, pdst_, st_));
     GemmArgs g{};
-    g.A = Hb_; g.lda = KP; g.Bt = Wp_; g.ldb = KP; g.M = M; g.N = D; g.K = KP;
+    g.A = Hb_; g.lda = KP; g.Bt = Wp_; g.ldb = KP; g.M = (int)p.patch_rows; g.N = D; g.K = KP;
     g.bias = b_p_; g.C = X_; g.ldc = D; g.N = D;
-    g.rowinfo = rowinfo_; g.pe = pe_; g.c_ref = c_ref_; g.c_other = c_other_;
+    g.rowinfo = prow_; g.rowdst = pdst_; g.pe = pe_; g.c_ref = c_ref_; g.c_other = c_other_;
     HIPCHECK(run_gemm(EPI_PATCH, g, MF_STAGE_PATCH));
+    if (!p.dups.empty()) {
+      prof_begin();
+      HIPCHECK(copy_embedded(frames, dups, (int)p.dups.size(), p.max_npad, X_, D, c_ref_, c_other_, st_));
+      prof_end(MF_STAGE_PATCH);
+    }
     // fp8: activations feeding the QKV and MLP GEMMs are quantised per window (dynamic scales)
     const int nwin = (int)p.gsegs.size();
     auto quant = [&](const void* y, int C, unsigned char* q, float* srow) {
@@ -867,7 +902,7 @@ class HipExecutor : public Executor {
     auto F = [this](void* p) { dfree(p); };
     F(wdev_); F(Wp_); F(H1t_);
     for (auto& L : layers_) { F(L.Wqkv); F(L.Wo); F(L.W1); F(L.W2); }
-    F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(rowframe_); F(win_scale_); F(Q_); F(K_); F(Vt_);
+    F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(rowframe_); F(prow_); F(pdst_); F(win_scale_); F(Q_); F(K_); F(Vt_);
     F(Wd_); F(bd_);
     F(Y8_); F(H8_); F(srow_); F(srow2_); F(amax_); F(wscale_); F(wamax_); F(Q8_); F(K8_); F(QE_); F(KE_);
     F(camln_); F(camg_); F(pose9_); F(tloc_); F(res_); F(keys_); F(psum_); F(pe_); F(tab_dev_);
@@ -921,6 +956,9 @@ class HipExecutor : public Executor {
   void *Y_ = nullptr, *O_ = nullptr, *Hb_ = nullptr, *Q_ = nullptr, *K_ = nullptr, *Vt_ = nullptr;
   int32_t* rowinfo_ = nullptr;
   int32_t* rowframe_ = nullptr;    // token row -> frame index of the batch (im2col)
+  int32_t* prow_ = nullptr;        // patch matrix row -> rowinfo of its token row
+  int32_t* pdst_ = nullptr;        // patch matrix row -> token row
+  int64_t reused_ = 0;             // frames of the last batch that took an earlier window's embedding
   double* win_scale_ = nullptr;    // per chained window: the anchoring's translation scale factor
   bool depth_head_ = false;
   const float *lnd_g_ = nullptr, *lnd_b_ = nullptr;

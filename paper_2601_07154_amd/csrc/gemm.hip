@@ -115,6 +115,7 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
       if (m >= a.M) continue;
       const int32_t ri = a.rowinfo[m];
       const int kind = (ri >> 30) & 3;
+      float* crow = (float*)a.C + (a.rowdst ? (int64_t)a.rowdst[m] : (int64_t)m) * a.ldc;
 #pragma unroll
       for (int j = 0; j < WN; ++j)
 #pragma unroll
@@ -126,7 +127,7 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
           else if (kind == 1) o = *(const f32x4*)(a.c_ref + n);
           else if (kind == 2) o = *(const f32x4*)(a.c_other + n);
           else o = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-          *(f32x4*)((float*)a.C + (int64_t)m * a.ldc + n) = o;
+          *(f32x4*)(crow + n) = o;
         }
     }
   } else if constexpr (TC) {

@@ -29,8 +29,9 @@ struct GemmArgs {
   float qscale;                    // EPI_QKV: factor on the q block before its rounding (0 reads as 1)
   // fp8 operands: per-row scale of A [M] and the scale of B [1] (device); null otherwise
   const float* ascale; const float* bscale;
-  // EPI_PATCH: per-row kind/PE row (rowinfo), PE table [rows][N] fp32, camera tokens
-  const int32_t* rowinfo; const float* pe; const float* c_ref; const float* c_other;
+  // EPI_PATCH: per-row kind/PE row (rowinfo), PE table [rows][N] fp32, camera tokens; rowdst
+  // (nullable): the X row each A row is written to
+  const int32_t* rowinfo; const float* pe; const float* c_ref; const float* c_other; const int32_t* rowdst;
   // EPI_DEPTH: rowinfo as above, each row's frame in the batch, the frames' targets, and the windows'
   // scale factors; C = depth maps: dst[(14 py + n / 14) W + 14 px + n % 14] = scale exp(acc + bias)
   // for output columns n < 196 of a patch row (py, px)
@@ -75,11 +76,18 @@ struct FrameDesc {
   int32_t npad;           // rows reserved for the frame
   int32_t first;          // 1 for the first frame of its window (reference camera token)
   int32_t pe_base;        // first row of the frame's resolution in the PE arena
+  int32_t patch_base;     // first row of its patch matrix rows, or -1: the frame is embedded already
+  int32_t src_base;       // (patch_base -1) token row of the earlier occurrence whose rows it takes
 };
-// Writes the normalised patch matrix A [rows, kpad] (dtype), rowinfo and (if not null) rowframe
-// (the row's frame index in `frames`) for every token row.
+// Writes rowinfo and (if not null) rowframe (the row's frame index in `frames`) for every token
+// row, and for every frame with patch_base >= 0 its rows of the patch matrix A [rows, kpad] (dtype)
+// at patch_base.., with prow (the rows' rowinfo) and pdst (the token row each patch row is for).
 hipError_t im2col(Dtype dt, const FrameDesc* frames, int nframes, int max_npad, void* A, int kpad,
-                  int32_t* rowinfo, int32_t* rowframe, hipStream_t s);
+                  int32_t* rowinfo, int32_t* rowframe, int32_t* prow, int32_t* pdst, hipStream_t s);
+// Frames embedded earlier in the batch (patch_base -1): token rows 1.. copied from src_base's rows
+// (patch rows and padding, fp32 X [rows][dim]), row 0 set to the frame's own camera token.
+hipError_t copy_embedded(const FrameDesc* frames, const int32_t* dups, int ndups, int max_npad, float* X, int dim,
+                         const float* c_ref, const float* c_other, hipStream_t s);
 hipError_t make_pe(float* pe, int gh, int gw, int dim, hipStream_t s);
 
 // ---------------------------------------------------------------- weights

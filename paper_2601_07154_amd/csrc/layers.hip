@@ -71,20 +71,30 @@ template <typename T>
 __global__ __launch_bounds__(256) void im2col_kernel(const FrameDesc* __restrict__ frames,
                                                      T* __restrict__ A, int kpad,
                                                      int32_t* __restrict__ rowinfo,
-                                                     int32_t* __restrict__ rowframe) {
+                                                     int32_t* __restrict__ rowframe,
+                                                     int32_t* __restrict__ prow, int32_t* __restrict__ pdst) {
   const FrameDesc fd = frames[blockIdx.y];
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= fd.npad) return;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)fd.token_base + j;
-  if (rowframe && lane == 0) rowframe[row] = (int32_t)blockIdx.y;
-  T* ar = A + row * kpad;
+  const int p = j - 1;
+  const int32_t info = (j == 0) ? (fd.first ? (1 << 30) : (2 << 30)) : (j > fd.P ? (3 << 30) : fd.pe_base + p);
+  if (lane == 0) {
+    rowinfo[row] = info;
+    if (rowframe) rowframe[row] = (int32_t)blockIdx.y;
+  }
+  if (fd.patch_base < 0) return;                 // embedded already: its rows are copied afterwards
+  const int64_t arow = (int64_t)fd.patch_base + j;
+  if (lane == 0) {
+    prow[arow] = info;
+    pdst[arow] = (int32_t)row;
+  }
+  T* ar = A + arow * kpad;
   if (j == 0 || j > fd.P) {
     for (int k = lane; k < kpad; k += 64) ar[k] = from_f32<T>(0.0f);
-    if (lane == 0) rowinfo[row] = j == 0 ? (fd.first ? (1 << 30) : (2 << 30)) : (3 << 30);
     return;
   }
-  const int p = j - 1;
   const int py = p / fd.gw, px = p - py * fd.gw;
   const float mean[3] = {0.485f, 0.456f, 0.406f};
   const float istd[3] = {1.0f / 0.229f, 1.0f / 0.224f, 1.0f / 0.225f};
@@ -97,17 +107,41 @@ __global__ __launch_bounds__(256) void im2col_kernel(const FrameDesc* __restrict
     }
     ar[k] = from_f32<T>(v);
   }
-  if (lane == 0) rowinfo[row] = fd.pe_base + p;
 }
 
 hipError_t im2col(Dtype dt, const FrameDesc* frames, int nframes, int max_npad, void* A, int kpad,
-                  int32_t* rowinfo, int32_t* rowframe, hipStream_t s) {
+                  int32_t* rowinfo, int32_t* rowframe, int32_t* prow, int32_t* pdst, hipStream_t s) {
   if (nframes <= 0) return hipSuccess;
   const dim3 grid((unsigned)((max_npad + 3) / 4), (unsigned)nframes);
   if (dt == DT_BF16)
-    hipLaunchKernelGGL((im2col_kernel<bf16>), grid, dim3(256), 0, s, frames, (bf16*)A, kpad, rowinfo, rowframe);
+    hipLaunchKernelGGL((im2col_kernel<bf16>), grid, dim3(256), 0, s, frames, (bf16*)A, kpad, rowinfo, rowframe, prow,
+                       pdst);
   else
-    hipLaunchKernelGGL((im2col_kernel<float>), grid, dim3(256), 0, s, frames, (float*)A, kpad, rowinfo, rowframe);
+    hipLaunchKernelGGL((im2col_kernel<float>), grid, dim3(256), 0, s, frames, (float*)A, kpad, rowinfo, rowframe, prow,
+                       pdst);
+  return hipGetLastError();
+}
+
+// Block (x, d): rows x*4 .. x*4+3 of duplicate frame dups[d] (one wave per row, dim / 64 floats per lane).
+__global__ __launch_bounds__(256) void copy_embedded_kernel(const FrameDesc* __restrict__ frames,
+                                                            const int32_t* __restrict__ dups, float* __restrict__ X,
+                                                            int dim, const float* __restrict__ c_ref,
+                                                            const float* __restrict__ c_other) {
+  const FrameDesc fd = frames[dups[blockIdx.y]];
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= fd.npad) return;
+  const int lane = threadIdx.x & 63;
+  float* dst = X + ((int64_t)fd.token_base + j) * dim;
+  const float* src = j == 0 ? (fd.first ? c_ref : c_other) : X + ((int64_t)fd.src_base + j) * dim;
+  for (int c = lane * 4; c < dim; c += 256) *(f32x4*)(dst + c) = *(const f32x4*)(src + c);
+}
+
+hipError_t copy_embedded(const FrameDesc* frames, const int32_t* dups, int ndups, int max_npad, float* X, int dim,
+                         const float* c_ref, const float* c_other, hipStream_t s) {
+  if (ndups <= 0) return hipSuccess;
+  if (dim % 4) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((max_npad + 3) / 4), (unsigned)ndups);
+  hipLaunchKernelGGL(copy_embedded_kernel, grid, dim3(256), 0, s, frames, dups, X, dim, c_ref, c_other);
   return hipGetLastError();
 }
 

@@ -302,6 +302,43 @@ def test_graph_key_separates_batches_with_equal_counts():
         np.testing.assert_array_equal(mp, rmp)
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_shared_frame_embedding_equals_separate_batches(precision):
+    """Consecutive windows share their overlap frames (Sec. 2.2).  A stream pushed whole runs its four
+    windows in one batch, where every overlap frame takes the earlier window's patch embedding (12
+    frames); pushed a stride at a time, each window runs in a batch of its own and embeds all its
+    frames.  The records and maps are the same bit for bit."""
+    torch = torch_cuda()
+    m = mf()
+    model = mf_synth.ModelConfig(4, 384, 6, 1536)
+    blob = mf_synth.make_weights(model, 5)
+    H, W, L, O, N = 112, 168, 8, 4, 20
+    K = (120.0, 120.0, W / 2, H / 2)
+    frames = torch.from_numpy(mf_synth.make_frames(N, H, W, 17)).cuda()
+
+    def run(pieces):
+        eng = m.Engine.from_model(model, blob, precision=precision, max_tokens=8192, graphs=False)
+        sid = eng.open_stream(H, W, L, O, K, sigma=300.0, ring_frames=N, result_frames=N)
+        for i, (a, b) in enumerate(pieces):
+            eng.push_frames(sid, frames[a:b], eos=i == len(pieces) - 1)
+            eng.sync()
+        mp = np.zeros((N, H, W), np.float32)
+        r, _ = eng.poll(sid, N, mp)
+        eng.poll(sid, 1)
+        st = eng.stats()
+        eng.close()
+        assert list(r["frame"]) == list(range(N))
+        return r, mp, st
+
+    whole, whole_maps, st_whole = run([(0, N)])
+    apart, apart_maps, st_apart = run([(0, L)] + [(a, a + L - O) for a in range(L, N, L - O)])
+    assert st_whole["batches_run"] == 1 and st_whole["frames_embed_shared"] == 3 * O
+    assert st_apart["batches_run"] == 4 and st_apart["frames_embed_shared"] == 0
+    for f in ("T_w2c", "pose9", "a_world", "u", "v", "valid", "peak_x", "peak_y", "window"):
+        np.testing.assert_array_equal(whole[f], apart[f], err_msg=f)
+    np.testing.assert_array_equal(whole_maps, apart_maps)
+
+
 @pytest.mark.parametrize("threaded", [False, True])
 def test_torch_allocator_matches_default(threaded):
     """With allocator="torch" every device buffer of the engine comes from torch's caching
