@@ -551,7 +551,21 @@ static hipError_t dispatch(Epi epi, const GemmArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// The pointers each epilogue dereferences: a launch without them is refused on the host (the
+// kernels would otherwise fault on the device).
+static bool epilogue_args_ok(Epi epi, const GemmArgs& a) {
+  if (!a.A || !a.Bt) return false;
+  switch (epi) {
+    case EPI_RESID: case EPI_GELU: case EPI_STORE: return a.C != nullptr;
+    case EPI_QKV: return a.q && a.k && a.vt && a.heads > 0 && a.hd > 0 && a.mpad > 0;
+    case EPI_PATCH: return a.C && a.rowinfo && a.pe && a.c_ref && a.c_other && a.bias;
+    case EPI_DEPTH: return a.rowinfo && a.rowframe && a.dframes && a.win_scale && a.bias;
+  }
+  return false;
+}
+
 hipError_t gemm(Dtype dt, Epi epi, const GemmArgs& a, hipStream_t s) {
+  if (!epilogue_args_ok(epi, a)) return hipErrorInvalidValue;
   if (dt == DT_FP8) {
     if (epi == EPI_PATCH || epi == EPI_STORE || epi == EPI_DEPTH) return hipErrorInvalidValue;   // not used with fp8
     if (!a.ascale || !a.bscale) return hipErrorInvalidValue;
