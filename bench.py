@@ -34,6 +34,11 @@ SIGMA = 1000.0   # focus-map spread per unit of |a_w|, the value the stored orac
 GEMM_STAGES = ("qkv", "out_proj", "fc1", "fc2")
 
 
+def progress(msg: str) -> None:
+    """A line on stderr per finished leg (the JSON result stays the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -177,8 +182,9 @@ def run_gpu(inp: Inputs, precision: str, steps: int, warmup: int, profile: bool 
     for sid in sids:   # drain: releases the streams
         eng.poll(sid, 1)
     first = recs[:wl.frames]
+    shared = eng.stats()["frames_embed_shared"] / (steps + warmup)
     eng.close()
-    return dict(frames=n, seconds=dt, prof=prof, stages=stages, first=first,
+    return dict(frames=n, seconds=dt, prof=prof, stages=stages, first=first, shared_per_step=shared,
                 batch_ms=(recs["t_ready"] - recs["t_push"]).max() * 1e3)
 
 
@@ -384,8 +390,10 @@ def main():
         torch.cuda.synchronize()
         del src, flush, dst
     inp = Inputs(wl)
+    progress(f"inputs ready: {wl.name}")
     r = run_gpu(inp, args.precision, args.steps, args.warmup)
     fps = r["frames"] / r["seconds"]
+    progress(f"{args.precision} eager leg: {fps:.1f} frames/s")
     ms_step = r["seconds"] * 1e3 / args.steps
     nwin = len(window_sizes(wl.frames, wl.window, wl.overlap))
     res = {
@@ -400,11 +408,14 @@ def main():
         # a step pushes a whole stream at once: this is the time from that push to its last result
         # (per-frame serving latency is the --serve line's)
         "stream_batch_latency_ms": float(r["batch_ms"]),
+        # overlap frames of consecutive windows whose patch embedding is taken from the earlier window
+        "patch_embedding_shared_frames_per_step": r["shared_per_step"],
         "path_tflops": path_flops(wl) * args.steps / r["seconds"] / 1e12,
     }
     if not args.no_graphs:
         rg = run_gpu(inp, args.precision, args.steps, args.warmup, profile=False, graphs=True)
         res["value_graphs_unprofiled"] = rg["frames"] / rg["seconds"]
+        progress(f"{args.precision} graph leg: {res['value_graphs_unprofiled']:.1f} frames/s")
     prof, stages = r["prof"], r["stages"]
     calls = max(1, prof["attn_global_calls"])
     avg_ms = prof["attn_global_ms"] / calls
@@ -449,6 +460,7 @@ def main():
         gb = sum(stages[k][0] for k in GEMM_STAGES) / args.steps
         if g8 > 0 and gb > 0:
             res["fp8_gemm_speedup_vs_bf16"] = gb / g8
+        progress(f"fp8 legs: {res['fp8_value']:.1f} frames/s")
     if not args.no_fp32 and args.precision != "fp32":
         v32, dt32, st32 = run_fp32_single_stream(inp)
         res["fp32_single_stream"] = {"value": v32, "unit": "frames/s", "seconds": dt32,
@@ -456,8 +468,10 @@ def main():
                                      "what": "plain FP32 path: fp32 operands on fp32 MFMA, one window per batch, "
                                              "one stream, no hipGraphs"}
         res["speedup_vs_fp32_single_stream"] = fps / v32
+        progress(f"fp32 single-stream leg: {v32:.1f} frames/s")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, inp.blob)
+        progress("cpu baseline done")
     print(json.dumps(res))
 
 
