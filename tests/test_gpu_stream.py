@@ -303,16 +303,18 @@ def test_graph_key_separates_batches_with_equal_counts():
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp8"])
-def test_shared_frame_embedding_equals_separate_batches(precision):
+@pytest.mark.parametrize("H,W", [(112, 168), (14, 28)])
+def test_shared_frame_embedding_equals_separate_batches(precision, H, W):
     """Consecutive windows share their overlap frames (Sec. 2.2).  A stream pushed whole runs its four
     windows in one batch, where every overlap frame takes the earlier window's patch embedding (12
     frames); pushed a stride at a time, each window runs in a batch of its own and embeds all its
-    frames.  The records and maps are the same bit for bit."""
+    frames.  The records and maps are the same bit for bit.  14 x 28 frames: 2 patches, 8 token rows
+    per frame (fewer rows than one 32-key attention step)."""
     torch = torch_cuda()
     m = mf()
     model = mf_synth.ModelConfig(4, 384, 6, 1536)
     blob = mf_synth.make_weights(model, 5)
-    H, W, L, O, N = 112, 168, 8, 4, 20
+    L, O, N = 8, 4, 20
     K = (120.0, 120.0, W / 2, H / 2)
     frames = torch.from_numpy(mf_synth.make_frames(N, H, W, 17)).cuda()
 
