@@ -511,9 +511,12 @@ class HipExecutor : public Executor {
   }
   uint64_t workspace_bytes() const {
     const uint64_t D = D_, wide = std::max<int64_t>(F_, KP);
-    const uint64_t f8 = (fp8_ ? (uint64_t)mcap_ * (D + F_ + 8) : 0) +
+    // fp8: Y8, H8, the two row-scale arrays and the LayerNorm row maxima; E4M3 q / k and exponents
+    const uint64_t f8 = (fp8_ ? (uint64_t)mcap_ * (D + F_ + 12) : 0) +
                         (fp8_attn_ ? (uint64_t)mpad_ * 2 * (D + (uint64_t)H_) : 0);
-    return f8 + (uint64_t)mcap_ * (D * 4 + D * es_ + D * es_ + wide * es_ + 4 + 4) + (uint64_t)mpad_ * 3 * D * es_ +
+    // per token row: X, Y, O, the hidden, and four int32 maps (rowinfo, rowframe, patch row info
+    // and destination)
+    return f8 + (uint64_t)mcap_ * (D * 4 + D * es_ + D * es_ + wide * es_ + 4 * 4) + (uint64_t)mpad_ * 3 * D * es_ +
            (uint64_t)fcap_ * (2 * D * 4 + 9 * 4 + 16 * 8 + sizeof(mf_focus) * 2 + 8 + 8) + (64u << 20);
   }
 
@@ -626,6 +629,7 @@ class HipExecutor : public Executor {
       HIPCHECK(dmalloc(&H8_, (size_t)mcap_ * F_));
       HIPCHECK(dmalloc(&srow_, (size_t)mcap_ * 4));
       HIPCHECK(dmalloc(&srow2_, (size_t)mcap_ * 4));
+      HIPCHECK(dmalloc(&rowmax_, (size_t)mcap_ * 4));
       HIPCHECK(dmalloc(&amax_, (size_t)fcap_ * 4));
     }
     HIPCHECK(dmalloc(&camln_, (size_t)fcap_ * D * 4));
@@ -757,15 +761,18 @@ class HipExecutor : public Executor {
     }
     // fp8: activations feeding the QKV and MLP GEMMs are quantised per window (dynamic scales)
     const int nwin = (int)p.gsegs.size();
-    auto quant = [&](const void* y, int C, unsigned char* q, float* srow) {
+    // (the LayerNorm outputs' window maxima come from its per-row maxima: rowmax non-null)
+    auto quant = [&](const void* y, int C, unsigned char* q, float* srow, const float* rowmax) {
       prof_begin();
-      const hipError_t r = window_quant_fp8((const __bf16*)y, C, gsegs, nwin, p.max_rows, amax_, q, srow, st_);
+      const hipError_t r =
+          rowmax ? window_quant_fp8_rows((const __bf16*)y, C, gsegs, nwin, p.max_rows, rowmax, amax_, q, srow, st_)
+                 : window_quant_fp8((const __bf16*)y, C, gsegs, nwin, p.max_rows, amax_, q, srow, st_);
       prof_end(MF_STAGE_QUANT_FP8);
       return r;
     };
     auto ln = [&](const float* g_, const float* b_) {
       prof_begin();
-      const hipError_t r = layernorm(dt_, X_, Y_, g_, b_, M, D, nullptr, st_);
+      const hipError_t r = layernorm(dt_, X_, Y_, g_, b_, M, D, nullptr, st_, fp8_ ? rowmax_ : nullptr);
       prof_end(MF_STAGE_LAYERNORM);
       return r;
     };
@@ -778,7 +785,7 @@ class HipExecutor : public Executor {
       q.qscale = attention_q_scale(hd_);
       if (fp8_attn_) { q.q8 = Q8_; q.k8 = K8_; q.qe8 = QE_; q.ke8 = KE_; }
       if (fp8_) {
-        HIPCHECK(quant(Y_, D, Y8_, srow_));
+        HIPCHECK(quant(Y_, D, Y8_, srow_, rowmax_));
         q.A = Y8_;
         q.ascale = srow_;
         q.bscale = wscale_ + 3 * l;
@@ -802,7 +809,7 @@ class HipExecutor : public Executor {
       f1.A = Y_; f1.lda = D; f1.Bt = L.W1; f1.ldb = D; f1.M = M; f1.N = F_; f1.K = D; f1.bias = L.b_1;
       f1.C = Hb_; f1.ldc = F_;
       if (fp8_) {
-        HIPCHECK(quant(Y_, D, Y8_, srow_));
+        HIPCHECK(quant(Y_, D, Y8_, srow_, rowmax_));
         f1.A = Y8_;
         f1.ascale = srow_;
         f1.bscale = wscale_ + 3 * l + 1;
@@ -812,7 +819,7 @@ class HipExecutor : public Executor {
       f2.A = Hb_; f2.lda = F_; f2.Bt = L.W2; f2.ldb = F_; f2.M = M; f2.N = D; f2.K = F_; f2.bias = L.b_2;
       f2.C = X_; f2.ldc = D;
       if (fp8_) {
-        HIPCHECK(quant(Hb_, F_, H8_, srow2_));
+        HIPCHECK(quant(Hb_, F_, H8_, srow2_, nullptr));
         f2.A = H8_;
         f2.ascale = srow2_;
         f2.bscale = wscale_ + 3 * l + 2;
@@ -904,7 +911,7 @@ class HipExecutor : public Executor {
     for (auto& L : layers_) { F(L.Wqkv); F(L.Wo); F(L.W1); F(L.W2); }
     F(X_); F(Y_); F(O_); F(Hb_); F(rowinfo_); F(rowframe_); F(prow_); F(pdst_); F(win_scale_); F(Q_); F(K_); F(Vt_);
     F(Wd_); F(bd_);
-    F(Y8_); F(H8_); F(srow_); F(srow2_); F(amax_); F(wscale_); F(wamax_); F(Q8_); F(K8_); F(QE_); F(KE_);
+    F(Y8_); F(H8_); F(srow_); F(srow2_); F(rowmax_); F(amax_); F(wscale_); F(wamax_); F(Q8_); F(K8_); F(QE_); F(KE_);
     F(camln_); F(camg_); F(pose9_); F(tloc_); F(res_); F(keys_); F(psum_); F(pe_); F(tab_dev_);
     if (res_host_) hipHostFree(res_host_);
     if (tab_host_) hipHostFree(tab_host_);
@@ -988,6 +995,7 @@ class HipExecutor : public Executor {
   bool fp8_attn_ = false;
   unsigned char *Q8_ = nullptr, *K8_ = nullptr, *QE_ = nullptr, *KE_ = nullptr;
   float *srow_ = nullptr, *srow2_ = nullptr, *wscale_ = nullptr;
+  float* rowmax_ = nullptr;        // fp8: max |Y| of each token row, written by the LayerNorm
   unsigned *amax_ = nullptr, *wamax_ = nullptr;
   struct GraphEntry {
     hipGraphExec_t exec = nullptr;

@@ -64,9 +64,10 @@ hipError_t attention_fp8qk(const unsigned char* q8, const unsigned char* qe8, co
                            const AttnSeg* segs, const AttnWork* work, int nwork, hipStream_t s);
 
 // ---------------------------------------------------------------- LayerNorm (fp32 in, dtype out)
-// rows: optional gather table (out row i <- in row rows[i]).
+// rows: optional gather table (out row i <- in row rows[i]); rowmax (optional): max |y| of every
+// output row as stored, [nrows] fp32.
 hipError_t layernorm(Dtype out_dt, const float* x, void* y, const float* g, const float* b,
-                     int64_t nrows, int dim, const int32_t* rows, hipStream_t s);
+                     int64_t nrows, int dim, const int32_t* rows, hipStream_t s, float* rowmax = nullptr);
 
 // ---------------------------------------------------------------- patch embedding input
 struct FrameDesc {
@@ -100,6 +101,10 @@ hipError_t convert_transpose(Dtype dt, const float* w, int rows, int cols, void*
 // the scale of row m's window.  amax: [nwin] scratch (cleared here).  y [rows][C] bf16, C % 16 == 0.
 hipError_t window_quant_fp8(const __bf16* y, int C, const AttnSeg* wins, int nwin, int max_rows, unsigned* amax,
                             unsigned char* q, float* srow, hipStream_t s);
+// The same with the rows' maxima already known (the LayerNorm's rowmax output): the window amax is
+// a reduction over [rows] floats instead of a pass over y.
+hipError_t window_quant_fp8_rows(const __bf16* y, int C, const AttnSeg* wins, int nwin, int max_rows,
+                                 const float* rowmax, unsigned* amax, unsigned char* q, float* srow, hipStream_t s);
 // Static per-tensor weight scale: out[c * ld + r] = E4M3(w[r][c] / s), s = amax(|w|) / 448 -> *scale.
 hipError_t quantize_weight_fp8(const float* w, int rows, int cols, unsigned char* out, int ld, unsigned* amax_tmp,
                                float* scale, hipStream_t s);

@@ -7,11 +7,12 @@ namespace mf {
 
 // ------------------------------------------------------------------ LayerNorm, one wave per row
 // (x - mean) / sqrt(var + 1e-6) * g + b with fp32 statistics (two passes over registers).
+// rowmax (nullable): max |y| of each written row (the values as stored), for the fp8 window scales.
 template <typename T, int VPL>
 __global__ __launch_bounds__(256) void ln_kernel(const float* __restrict__ x, T* __restrict__ y,
                                                  const float* __restrict__ g,
                                                  const float* __restrict__ b, int64_t nrows,
-                                                 const int32_t* __restrict__ rows) {
+                                                 const int32_t* __restrict__ rows, float* __restrict__ rowmax) {
   constexpr int D = VPL * 64;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= nrows) return;
@@ -33,34 +34,41 @@ __global__ __launch_bounds__(256) void ln_kernel(const float* __restrict__ x, T*
   }
   const float rstd = rsqrtf(wave_sum(q) * (1.0f / D) + 1e-6f);
   T* yr = y + r * D;
+  float mx = 0.0f;
 #pragma unroll
   for (int i = 0; i < VPL; ++i) {
     const int c = i * 64 + lane;
-    yr[c] = from_f32<T>((v[i] - mean) * rstd * g[c] + b[c]);
+    const T o = from_f32<T>((v[i] - mean) * rstd * g[c] + b[c]);
+    yr[c] = o;
+    mx = fmaxf(mx, fabsf(to_f32(o)));
+  }
+  if (rowmax) {
+    mx = wave_max(mx);
+    if (lane == 0) rowmax[r] = mx;
   }
 }
 
 template <typename T>
 static hipError_t ln_launch(const float* x, void* y, const float* g, const float* b,
-                            int64_t nrows, int dim, const int32_t* rows, hipStream_t s) {
+                            int64_t nrows, int dim, const int32_t* rows, float* rowmax, hipStream_t s) {
   const dim3 grid((unsigned)((nrows + 3) / 4));
   switch (dim) {
-    case 128: hipLaunchKernelGGL((ln_kernel<T, 2>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
-    case 256: hipLaunchKernelGGL((ln_kernel<T, 4>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
-    case 384: hipLaunchKernelGGL((ln_kernel<T, 6>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
-    case 512: hipLaunchKernelGGL((ln_kernel<T, 8>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
-    case 768: hipLaunchKernelGGL((ln_kernel<T, 12>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
-    case 1024: hipLaunchKernelGGL((ln_kernel<T, 16>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows); break;
+    case 128: hipLaunchKernelGGL((ln_kernel<T, 2>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows, rowmax); break;
+    case 256: hipLaunchKernelGGL((ln_kernel<T, 4>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows, rowmax); break;
+    case 384: hipLaunchKernelGGL((ln_kernel<T, 6>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows, rowmax); break;
+    case 512: hipLaunchKernelGGL((ln_kernel<T, 8>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows, rowmax); break;
+    case 768: hipLaunchKernelGGL((ln_kernel<T, 12>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows, rowmax); break;
+    case 1024: hipLaunchKernelGGL((ln_kernel<T, 16>), grid, dim3(256), 0, s, x, (T*)y, g, b, nrows, rows, rowmax); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t layernorm(Dtype out_dt, const float* x, void* y, const float* g, const float* b,
-                     int64_t nrows, int dim, const int32_t* rows, hipStream_t s) {
+                     int64_t nrows, int dim, const int32_t* rows, hipStream_t s, float* rowmax) {
   if (nrows <= 0) return hipSuccess;
-  return out_dt == DT_BF16 ? ln_launch<bf16>(x, y, g, b, nrows, dim, rows, s)
-                           : ln_launch<float>(x, y, g, b, nrows, dim, rows, s);
+  return out_dt == DT_BF16 ? ln_launch<bf16>(x, y, g, b, nrows, dim, rows, rowmax, s)
+                           : ln_launch<float>(x, y, g, b, nrows, dim, rows, rowmax, s);
 }
 
 // ------------------------------------------------------------------ patch matrix
@@ -300,6 +308,34 @@ __global__ __launch_bounds__(256) void window_quant_kernel(const bf16* __restric
     *(u32x4*)(qrow + c) = o;
   }
   if ((threadIdx.x & 15) == 0) srow[r] = s;
+}
+
+// amax[w] = the largest row maximum over window w's valid rows: one workgroup per window, so the
+// value is written whole (nothing to clear first).
+__global__ __launch_bounds__(256) void window_amax_rows_kernel(const float* __restrict__ rowmax,
+                                                               const AttnSeg* __restrict__ wins,
+                                                               unsigned* __restrict__ amax) {
+  const AttnSeg w = wins[blockIdx.x];
+  const int rows = w.nf * w.npad;
+  float mx = 0.0f;
+  for (int rel = threadIdx.x; rel < rows; rel += 256)
+    if ((rel % w.npad) < w.n) mx = fmaxf(mx, rowmax[w.base + rel]);
+  mx = wave_max(mx);
+  __shared__ float red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) amax[blockIdx.x] = __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+}
+
+hipError_t window_quant_fp8_rows(const bf16* y, int C, const AttnSeg* wins, int nwin, int max_rows,
+                                 const float* rowmax, unsigned* amax, fp8* q, float* srow, hipStream_t s) {
+  if (nwin <= 0) return hipSuccess;
+  if (C % 16 != 0 || !rowmax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(window_amax_rows_kernel, dim3((unsigned)nwin), dim3(256), 0, s, rowmax, wins, amax);
+  const int xb = (max_rows + 15) / 16;
+  hipLaunchKernelGGL(window_quant_kernel, dim3((unsigned)xb, (unsigned)nwin), dim3(256), 0, s, y, C, wins, amax, q,
+                     srow);
+  return hipGetLastError();
 }
 
 hipError_t window_quant_fp8(const bf16* y, int C, const AttnSeg* wins, int nwin, int max_rows, unsigned* amax,
