@@ -160,6 +160,14 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
               (f32x4){acc[i][2 * jh + j][4 * rg], acc[i][2 * jh + j][4 * rg + 1], acc[i][2 * jh + j][4 * rg + 2],
                       acc[i][2 * jh + j][4 * rg + 3]};
       __syncthreads();
+      // fp8 operands: the chunk's row scales are loaded before its first store (loads and stores
+      // share one in-order counter: a load issued after a store waits for that store)
+      float rsc[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        rsc[p] = 1.0f;
+        if constexpr (sizeof(T) == 1) rsc[p] = a.ascale[min(m0 + wr * 32 * WM + i * 32 + rr + 4 * p, a.M - 1)] * bs;
+      }
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         const int r = rr + 4 * p;
@@ -171,8 +179,7 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
           if (a.q8 && which < 2) {
             const bool ok = m < a.M;
             f32x4 v = *(const f32x4*)(stage + r * SR + c4);
-            const float sc = (ok && a.ascale) ? a.ascale[m] * bs : 1.0f;
-            v = (v * sc + bias4) * qs;
+            v = (v * rsc[p] + bias4) * qs;
             float mx = ok ? fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))) : 0.0f;
 #pragma unroll
             for (int o = 1; o < 16; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
@@ -188,8 +195,7 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
         }
         if (m < a.M) {
           f32x4 v = *(const f32x4*)(stage + r * SR + c4);
-          const float sc = a.ascale ? a.ascale[m] * bs : 1.0f;
-          v = v * sc + bias4;
+          v = v * rsc[p] + bias4;
           if constexpr (EPI == EPI_QKV) v = v * qs;
           if constexpr (EPI == EPI_RESID) {
             f32x4* c = (f32x4*)((float*)a.C + (int64_t)m * a.ldc + nb);
@@ -236,16 +242,22 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
                       acc[i][2 * jh + j][4 * rg + 3]};
       __syncthreads();
       const int mb = m0 + wr * 32 * WM + i * 32 + r4;
-      float sc[4];
+      // loads before stores (one in-order counter for both): row scales (fp8), the columns' biases
+      float sc[4], bnv[8];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) sc[e] = a.ascale ? a.ascale[min(mb + e, a.M - 1)] * bs : 1.0f;
+      for (int e = 0; e < 4; ++e) {
+        sc[e] = 1.0f;
+        if constexpr (sizeof(T) == 1) sc[e] = a.ascale[min(mb + e, a.M - 1)] * bs;
+      }
+#pragma unroll
+      for (int p = 0; p < 8; ++p) bnv[p] = a.bias[n0 + wc * 32 * WN + jh * 64 + cc + 8 * p];
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         const int c = cc + 8 * p;
         const int n = n0 + wc * 32 * WN + jh * 64 + c;
         const int nn = n - nbase;
         const int h = nn / a.hd, d = nn - h * a.hd;
-        const float bn = a.bias[n];
+        const float bn = bnv[p];
         const f32x4 v = *(const f32x4*)(stage + c * SV + r4);
         To* row = dst + ((int64_t)h * a.hd + d) * a.mpad;
         if (mb + 3 < a.M) {

@@ -312,26 +312,38 @@ __global__ __launch_bounds__(256) void window_quant_kernel(const bf16* __restric
 
 // amax[w] = the largest row maximum over window w's valid rows: one workgroup per window, so the
 // value is written whole (nothing to clear first).
-__global__ __launch_bounds__(256) void window_amax_rows_kernel(const float* __restrict__ rowmax,
-                                                               const AttnSeg* __restrict__ wins,
-                                                               unsigned* __restrict__ amax) {
+__global__ __launch_bounds__(1024) void window_amax_rows_kernel(const float* __restrict__ rowmax,
+                                                                const AttnSeg* __restrict__ wins,
+                                                                unsigned* __restrict__ amax) {
   const AttnSeg w = wins[blockIdx.x];
   const int rows = w.nf * w.npad;
   float mx = 0.0f;
-  for (int rel = threadIdx.x; rel < rows; rel += 256)
-    if ((rel % w.npad) < w.n) mx = fmaxf(mx, rowmax[w.base + rel]);
+  // four rows in flight per thread: the loop is bound by load latency, not bandwidth
+  for (int rel0 = threadIdx.x; rel0 < rows; rel0 += 4 * 1024) {
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int rel = rel0 + k * 1024;
+      v[k] = (rel < rows && (rel % w.npad) < w.n) ? rowmax[w.base + rel] : 0.0f;
+    }
+    mx = fmaxf(mx, fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+  }
   mx = wave_max(mx);
-  __shared__ float red[4];
+  __shared__ float red[16];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
-  if (threadIdx.x == 0) amax[blockIdx.x] = __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+  if (threadIdx.x == 0) {
+    float m = red[0];
+    for (int i = 1; i < 16; ++i) m = fmaxf(m, red[i]);
+    amax[blockIdx.x] = __float_as_uint(m);
+  }
 }
 
 hipError_t window_quant_fp8_rows(const bf16* y, int C, const AttnSeg* wins, int nwin, int max_rows,
                                  const float* rowmax, unsigned* amax, fp8* q, float* srow, hipStream_t s) {
   if (nwin <= 0) return hipSuccess;
   if (C % 16 != 0 || !rowmax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(window_amax_rows_kernel, dim3((unsigned)nwin), dim3(256), 0, s, rowmax, wins, amax);
+  hipLaunchKernelGGL(window_amax_rows_kernel, dim3((unsigned)nwin), dim3(1024), 0, s, rowmax, wins, amax);
   const int xb = (max_rows + 15) / 16;
   hipLaunchKernelGGL(window_quant_kernel, dim3((unsigned)xb, (unsigned)nwin), dim3(256), 0, s, y, C, wins, amax, q,
                      srow);
