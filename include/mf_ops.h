@@ -37,8 +37,9 @@ mf_status mf_forward_window(mf_engine* e, const float* frames_dev, int32_t S, in
  * take), 3 K, 4 Vt (layouts above; mpad is max_tokens_per_batch rounded up to 8,
  * plus 256), 5 attention output O
  * ([rows][dim]), 6 MLP hidden / patch matrix ([rows][max(mlp, 640)]); element type T of the
- * engine's precision except X; MF_FP8 engines with head dim 64 also keep 7 the E4M3 queries and
- * 8 keys ([heads][mpad][64] bytes) and 9, 10 their E8M0 row-scale bytes ([heads][mpad]).
+ * engine's precision except X; MF_FP8 engines with head dim 64 keep their queries and keys only as
+ * 7 the E4M3 queries and 8 keys ([heads][mpad][64] bytes) and 9, 10 their E8M0 row-scale bytes
+ * ([heads][mpad]); their buffers 2 and 3 are not written.
  * MF_EINVAL beyond the buffer or for a buffer the engine does not keep. */
 mf_status mf_debug_copy(mf_engine* e, int32_t which, void* host, size_t bytes);
 

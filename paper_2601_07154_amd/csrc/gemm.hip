@@ -191,6 +191,7 @@ MF_DEV void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[WM][WN], int m0, int 
               *(unsigned*)((which == 0 ? a.q8 : a.k8) + qoff + (int64_t)m * a.hd) = pk;
               if ((lane & 15) == 0) (which == 0 ? a.qe8 : a.ke8)[hrow + m] = (unsigned char)(e + 127);
             }
+            continue;   // the attention reads these rows only in E4M3: no bf16 copy
           }
         }
         if (m < a.M) {

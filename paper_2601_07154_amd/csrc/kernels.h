@@ -36,7 +36,7 @@ struct GemmArgs {
   // scale factors; C = depth maps: dst[(14 py + n / 14) W + 14 px + n % 14] = scale exp(acc + bias)
   // for output columns n < 196 of a patch row (py, px)
   const int32_t* rowframe; const DepthFrame* dframes; const double* win_scale;
-  // EPI_QKV, head dim 64, when q8 is set: the q and k blocks are also written as OCP E4M3 rows
+  // EPI_QKV, head dim 64, when q8 is set: the q and k blocks are written as OCP E4M3 rows (not to q / k)
   // [H][mpad][64] scaled per token and head by 2^-e (e the least integer with 448 2^e >= the row's
   // amax), with the E8M0 byte e + 127 in qe8 / ke8 [H][mpad]
   unsigned char *q8, *k8, *qe8, *ke8;

@@ -285,9 +285,13 @@ def test_attention_fp8_scores_match_fp64_on_decoded_operands(n, frames):
 
 
 def test_qkv_epilogue_writes_e4m3_rows_with_least_power_of_two_scales():
-    """In an fp8 engine the QKV projection also writes every query and key row of every head as E4M3
-    with an E8M0 exponent: decoded, it matches the bf16 rows of the same projection within an E4M3
-    rounding (plus the bf16 rounding), and each non-zero row reaches the top binade (|code| max in
+    """In an fp8 engine (head dim 64) the QKV projection writes every query and key row of every head
+    as E4M3 with an E8M0 exponent (and no bf16 copy).  Decoded, they match the oracle's E4M3
+    emulation of the same projection on the device's layer-0 tokens (LayerNorm in FP64 rounded to
+    bf16, the window's amax/448 activation scale and the weight's amax/448 scale, E4M3 operands,
+    FP64 products; queries times log2(e)/sqrt(hd)) within one E4M3 rounding of the output plus the
+    bf16 rounding (a few activations whose bf16 LayerNorm output differs in the last bit round to
+    another E4M3 code: at most 1 in 200), and each non-zero row reaches the top binade (|code| max in
     [224, 448]), which makes its exponent the least that fits."""
     torch = torch_cuda()
     m = mf()
@@ -295,20 +299,38 @@ def test_qkv_epilogue_writes_e4m3_rows_with_least_power_of_two_scales():
     blob = mf_synth.make_weights(MODEL, 2, std=0.05)
     frames = mf_synth.make_frames(S, H, W, 6)
     eng = m.Engine.from_model(MODEL, blob, precision="fp8", max_tokens=2048)
-    eng.forward_window(torch.from_numpy(frames).cuda(), max_layers=1)
-    hd, heads = 64, MODEL.heads
+    dfr = torch.from_numpy(frames).cuda()
+    _, _, tok0 = eng.forward_window(dfr, max_layers=0, want_tokens=True)
+    eng.forward_window(dfr, max_layers=1)
+    D, heads = MODEL.dim, MODEL.heads
+    hd = D // heads
+    assert hd == 64
     mpad = (2048 + 7) // 8 * 8 + 256
-    bf = lambda u: (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
     n = (H // 14) * (W // 14) + 1
     npad = m.rows_per_frame(H, W)
     rows = np.concatenate([np.arange(f * npad, f * npad + n) for f in range(S)])
-    for which, w8, we in ((2, 7, 9), (3, 8, 10)):
-        ref = bf(eng.debug_copy(which, (heads, mpad, hd), np.uint16))[:, rows]
+    lw = vit.unpack_weights(blob, MODEL.depth, MODEL.dim, MODEL.mlp)["layers"][0]
+    f32 = lambda x: np.asarray(x, dtype=np.float32)
+    y = vit.round_bf16(vit.layer_norm(tok0[rows].astype(np.float64), lw["ln1_g"], lw["ln1_b"])).astype(np.float32)
+    sa = f32(f32(np.max(np.abs(y))) / f32(448.0))
+    qa = vit.round_e4m3(f32(y * (f32(1.0) / sa)).astype(np.float64))
+    Wq = f32(lw["W_qkv"])
+    sw = f32(f32(np.max(np.abs(Wq))) / f32(448.0))
+    qw = vit.round_e4m3(f32(Wq * (f32(1.0) / sw)).astype(np.float64))
+    ref = (qa @ qw) * np.float64(f32(sa * sw)) + lw["b_qkv"]
+    c = np.float64(np.float32(math.log2(math.e) / math.sqrt(hd)))
+    for block, w8, we in ((0, 7, 9), (1, 8, 10)):
+        want = ref[:, block * D:(block + 1) * D].reshape(len(rows), heads, hd).transpose(1, 0, 2)
+        if block == 0:
+            want = want * c
         codes = eng.debug_copy(w8, (heads, mpad, hd), np.uint8)[:, rows]
         e = eng.debug_copy(we, (heads, mpad), np.uint8)[:, rows].astype(np.float64) - 127.0
         dec = e4m3_decode(codes) * 2.0 ** e[..., None]
-        tol = 2.0 ** -4 * np.abs(ref) + 2.0 ** -8 * np.abs(ref) + 2.0 ** (e[..., None] - 9)
-        assert (np.abs(dec - ref) <= tol).all(), np.abs(dec - ref).max()
+        tol = 2.0 ** -4 * np.abs(want) + 2.0 ** -7 * np.abs(want) + 2.0 ** (e[..., None] - 8)
+        bad = np.abs(dec - want) > tol
+        print(f"block {block}: max |dec - ref| / |ref|max {np.abs(dec - want).max() / np.abs(want).max():.3e}, "
+              f"beyond one E4M3 rounding {bad.sum()} of {bad.size}")
+        assert bad.sum() <= bad.size // 200
         top = np.abs(e4m3_decode(codes)).max(axis=-1)
         assert ((top >= 224.0) & (top <= 448.0)).all()
     eng.close()
