@@ -41,6 +41,7 @@ FIXTURES = {
     "large_bf16emu_w01": (mf_synth.LARGE, 2, "bf16"),
     "fp8_fp64_w0": (mf_synth.FP8, 1, "fp64"),
     "fp8_fp8emu_w0": (mf_synth.FP8, 1, "fp8"),
+    "fp8_bf16emu_w0": (mf_synth.FP8, 1, "bf16"),
 }
 
 
