@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 import mf_synth
-from gpu_util import dir_err_deg, mf, rot_err_deg, round_bf16, torch_cuda
+from gpu_util import (dir_err_deg, golden, golden_errors, mf, record_errors, rot_err_deg, round_bf16, run_stream_fused,
+                      summary, torch_cuda)
 from oracle import vit
 
 pytestmark = pytest.mark.gpu
@@ -103,6 +104,50 @@ def _layer0(blob):
         out[name] = np.asarray(blob[off:off + k], np.float64).reshape(shape)
         off += k
     return out
+
+
+def _focus_bounds(recs, ref, K):
+    """Focus errors that a run's own pose errors allow (first order): the acceleration is a second
+    difference of camera centres, so centre errors dp move its direction by at most 4 max|dp| / |a_w|
+    rad; the camera rotation's error adds its angle; where the oracle has |a_z| >= 0.5 |a| a pixel
+    moves by at most 4 f times the angle (d tan / d angle <= 4 there)."""
+    n = ref["T_w"].shape[0]
+    T = np.asarray(recs["T_w2c"])[:n].reshape(-1, 4, 4)
+    tr = ref["track"]
+    cg = -np.einsum("nji,nj->ni", T[:, :3, :3], T[:, :3, 3])
+    dp = np.linalg.norm(cg - tr["p"], axis=1)
+    dp3 = np.maximum(dp, np.maximum(np.r_[0, dp[:-1]], np.r_[0, 0, dp[:-2]]))
+    rot = np.radians(rot_err_deg(T[:, :3, :3], ref["T_w"][:, :3, :3]))
+    v = tr["valid"] & ((recs["valid"][:n] & 1) == 1)
+    cond = v & (np.abs(tr["a_c"][:, 2]) >= 0.5 * np.linalg.norm(tr["a_c"], axis=1))
+    ang = 4 * dp3 / np.maximum(np.linalg.norm(tr["a_w"], axis=1), 1e-300)
+    abound = np.degrees(ang[v])
+    pbound = 4 * max(K[0], K[1]) * (ang[cond] + rot[cond])
+    return abound, pbound
+
+
+def test_fp8_workload_window0_bf16_against_fp64():
+    """BF16, the whole 128-frame stream in one fused batch (the benchmark's launch configuration),
+    window 0's 48 emitted frames against the stored FP64 oracle output.  Rotation and translation
+    direction within max(2 deg, 3x the emulated-bf16 pose error of the large workload's stored
+    windows 0-1: the same 24-layer D=1024 model, whose bf16 roundings set the pose error; the FP8
+    workload's own emulated-bf16 run is not stored); the acceleration direction and focus point
+    within the first-order bounds the run's own centre and rotation errors allow."""
+    torch = torch_cuda()
+    ref = golden("fp8_fp64_w0")
+    emu_large = golden_errors(golden("large_bf16emu_w01"), golden("large_fp64_w01"))
+    blob = mf_synth.make_weights(WL.model, WL.seed_weights)
+    frames = torch.from_numpy(mf_synth.workload_frames(WL)).cuda()
+    recs = run_stream_fused(WL, "bf16", blob, frames)
+    del frames
+    e = record_errors(recs, ref)
+    abound, pbound = _focus_bounds(recs, ref, (WL.fx, WL.fy))
+    pose_lim = max(2.0, 3.0 * max(emu_large["rot"].max(), emu_large["tdir"].max()))
+    print("fp8 workload, bf16 vs FP64, window 0: " + summary(e))
+    print(f"limits: pose {pose_lim:.2f} deg, accel dir up to {abound.max():.1f} deg, focus up to {pbound.max():.0f} px")
+    assert e["rot"].max() <= pose_lim and e["tdir"].max() <= pose_lim
+    assert (e["adir"] <= abound + 1e-9).all()
+    assert (e["px"] <= pbound + 1e-9).all()
 
 
 def test_fp8_window_poses_against_bf16(setup):
